@@ -1,0 +1,298 @@
+#!/usr/bin/env python
+"""Throughput of the particle hot path on one MI355X.
+
+Workload (one "step" = one pass of advect + locate + re-sort over the store):
+64^3 uniform hex mesh on the unit cube, Q2 velocity = curl of a random
+8-mode Fourier vector potential (normalised to max nodal speed 1), 20
+particles per cell (5,242,880), FP64 locations, FP32 field evaluation,
+3 FP32 properties, classical RK4, dt = 0.5/64 (CFL 0.5).
+
+Prints ONE JSON line: particle-steps/s over exactly --steps timed steps
+(live particles summed over the steps), the HBM roofline of the dominant
+kernel (HIP events on the library's stream), the FP64 CPU oracle timed on a
+bounded sample, and extra measurements (adjoint/forward time ratio on the
+32^3 adjoint workload, batched vs per-problem, per-kernel times).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# algorithmic bytes per particle and launch (see the design notes): d = 3,
+# 3 float properties, int32 cell/key/slot/src, uint32 id
+def bytes_per_particle(kernel, dim=3, prop_bytes=12):
+    x = 8 * dim
+    return {
+        "advect": (x + x + 4) + (x + x + 4 + 4),                       # r: x, xr, cell; w: x, xr, key, slot
+        "place": 4 + 4 + 4 + 4,                                         # r: key, cell, slot; w: src
+        "gather": (4 + 4 + x + x + 4 + prop_bytes) + (x + x + 4 + 4 + prop_bytes),
+    }[kernel]
+
+
+def run_main(args):
+    import numpy as np
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Problem
+
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    cfg = I.config2(eval_f32=True)
+    mesh = cfg["mesh"]
+    n0 = cfg["xr"].shape[1]
+    log(f"[bench] workload {cfg['name']}: {mesh.n_cells} cells, {n0} particles")
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n0, n_prop=3, prop_dtype="float32")
+    dt = cfg["dt"]
+
+    def reseed():
+        p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+        p.stats_reset()
+        torch.cuda.synchronize()
+
+    # warmup
+    reseed()
+    if args.warmup:
+        p.advance(dt, args.warmup, L.PIC_RK4, L.PIC_F32)
+    torch.cuda.synchronize()
+    # timed region: exactly K steps from the seeded state
+    reseed()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.advance(dt, args.steps, L.PIC_RK4, L.PIC_F32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = p.stats()
+    elapsed = t1 - t0
+    psteps = st["particle_steps"]
+    value = psteps / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed * 1e3:.2f} ms, {psteps} particle-steps, live {st['live']}, "
+        f"lost {st['lost']}, moved/step {st['moved'] / max(1, args.steps):.0f}")
+
+    # per-kernel durations with HIP events on the library's stream (same K steps)
+    reseed()
+    p.profile(True)
+    p.advance(dt, args.steps, L.PIC_RK4, L.PIC_F32)
+    kernels = {}
+    for k in ("advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip"):
+        ms, n = p.profile_read(k)
+        kernels[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
+    p.profile(False)
+    st2 = p.stats()
+    dom = max(("advect", "gather", "place"), key=lambda k: kernels[k]["total_ms"])
+    avg_particles = st2["particle_steps"] / max(1, st2["steps"])
+    dof_bytes = mesh.n_nodes * 16 if dom == "advect" else 0
+    bytes_launch = avg_particles * bytes_per_particle(dom) + dof_bytes
+    achieved = bytes_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    step_bytes = avg_particles * (bytes_per_particle("advect") + bytes_per_particle("place") +
+                                  bytes_per_particle("gather")) + mesh.n_nodes * 16
+    step_ms = 1e3 * elapsed / args.steps
+    line = {
+        "metric": "particle-steps/s (advect+locate+sort)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 locations / f32 field evaluation",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "cells": mesh.n_cells, "particles": n0, "scheme": "rk4",
+                   "dt": dt, "eval": "f32", "n_prop": 3, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": kernels[dom]["avg_us"]},
+        "step_hbm_frac": step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels": kernels,
+        "stats": st,
+    }
+
+    # plain copy kernel of known size (calibrates the byte counters of a profiled run)
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    line["copy_gbs"] = 2 * a.numel() * 4 * 10 / (time.perf_counter() - t) / 1e9
+    del a, b
+    p.close()
+
+    if args.extras:
+        extras = {}
+        if "adjoint" in args.extras:
+            extras["adjoint"] = bench_adjoint(args)
+        if "batch" in args.extras:
+            extras["batch"] = bench_batch(args)
+        line["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args)
+    return line
+
+
+def bench_adjoint(args):
+    """Adjoint/forward time ratio on 32^3, 32 per cell (1,048,576 particles), RK4 x 50, checkpoints every 10."""
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Problem
+
+    cfg = I.config5()
+    mesh = cfg["mesh"]
+    n0 = cfg["xr"].shape[1]
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n0, n_prop=0)
+    ws = p.adjoint_workspace(cfg["steps"], cfg["ckpt_every"])
+    dt, ns = cfg["dt"], cfg["steps"]
+
+    def timed(fn, reps=3):
+        best = []
+        for _ in range(reps):
+            p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best.append(time.perf_counter() - t)
+        return sorted(best)[len(best) // 2]
+
+    fwd = timed(lambda: p.advance(dt, ns, L.PIC_RK4, L.PIC_F64))
+    dl = torch.ones((3, n0), dtype=torch.float64, device=p.device) * 1e-3
+    dU = torch.zeros((3, mesh.n_nodes), dtype=torch.float64, device=p.device)
+
+    def fwd_bwd():
+        p.advance_checkpointed(dt, ns, L.PIC_RK4, cfg["ckpt_every"], ws)
+        p.adjoint(dl, ws, dU)
+
+    both = timed(fwd_bwd)
+    r = {"workload": cfg["name"], "particles": n0, "forward_ms": fwd * 1e3, "forward_plus_adjoint_ms": both * 1e3,
+         "ratio": both / fwd}
+    log(f"[bench] adjoint: forward {fwd * 1e3:.1f} ms, checkpointed forward + adjoint {both * 1e3:.1f} ms")
+    p.close()
+    return r
+
+
+def bench_batch(args):
+    """64 problems stepped from one graph vs the same problems one by one (20 steps each)."""
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Batch, Problem
+
+    cfgs = I.config4()
+    probs = []
+    for c in cfgs:
+        m = c["mesh"]
+        q = Problem(0)
+        q.mesh_uniform(m.dim, m.n[: m.dim])
+        q.set_velocity(c["U"])
+        q.allocate(c["xr"].shape[1], n_prop=1)
+        probs.append(q)
+
+    def reseed():
+        for q, c in zip(probs, cfgs):
+            q.seed_reference(c["counts"], c["xr"], c["ids"])
+            q.stats_reset()
+        torch.cuda.synchronize()
+
+    total = sum(c["xr"].shape[1] for c in cfgs)
+    reseed()
+    t = time.perf_counter()
+    for q, c in zip(probs, cfgs):
+        q.advance(c["dt"], c["steps"], c["scheme"], L.PIC_F64)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t
+    ps_single = sum(q.stats()["particle_steps"] for q in probs)
+    bt = Batch(probs)
+    reseed()
+    bt.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 20)   # graph build + warm
+    torch.cuda.synchronize()
+    reseed()
+    t = time.perf_counter()
+    bt.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 20)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    ps_batch = sum(q.stats()["particle_steps"] for q in probs)
+    bt.close()
+    for q in probs:
+        q.close()
+    log(f"[bench] batch: {len(cfgs)} problems, {total} particles: per-problem {t_single * 1e3:.1f} ms, "
+        f"batched graph {t_batch * 1e3:.1f} ms")
+    return {"problems": len(cfgs), "particles": total, "per_problem_ms": t_single * 1e3, "batched_ms": t_batch * 1e3,
+            "speedup": t_single / t_batch, "particle_steps_per_s": ps_batch / t_batch,
+            "per_problem_particle_steps_per_s": ps_single / t_single}
+
+
+def cpu_baseline(args):
+    """FP64 oracle on the host cores: the first steps of the same workload."""
+    from oracle import oracle as O
+    from paper_1612_03369_amd import inputs as I
+
+    cfg = I.config2(eval_f32=True)
+    om = O.OracleMesh.uniform(cfg["mesh"])
+    st = O.seed(om, cfg["counts"], cfg["xr"], cfg["ids"], 3)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    s = O.Stats()
+    t = time.perf_counter()
+    steps = 0
+    psteps = 0
+    while steps < args.cpu_steps:
+        psteps += st.n
+        O.step(om, cfg["U"], cfg["dt"], 4, st, s)
+        steps += 1
+        if time.perf_counter() - t > 25.0:
+            break
+    el = time.perf_counter() - t
+    log(f"[bench] cpu oracle: {steps} steps, {psteps} particle-steps in {el:.1f} s on {threads} threads")
+    return {"value": psteps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {steps} steps of the full workload ({cfg['xr'].shape[1]} particles), FP64 evaluation"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--extras", default="adjoint,batch", help="comma list: adjoint,batch ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the hot path runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+    args.extras = [e for e in args.extras.split(",") if e]
+    line = run_main(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

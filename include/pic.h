@@ -1,0 +1,243 @@
+/*
+ * pic.h - C ABI of the MI355X particle-in-cell hot path.
+ *
+ * Method: Gassmoeller, Heien, Puckett, Bangerth, "Flexible and scalable
+ * particle-in-cell methods for massively parallel computations"
+ * (arXiv:1612.03369).  Section numbers below refer to that paper.
+ *
+ * The library advances particles through a Q2 (tensor-product quadratic
+ * Lagrange) velocity field on a quad/hex mesh, keeps the particle store sorted
+ * by owning cell, manages per-cell populations and interpolates particle
+ * properties to cells.  Every step of that path runs in HIP kernels built for
+ * gfx950; the host code only prepares meshes and launches kernels.
+ *
+ * Conventions
+ *  - Status codes: every call returns PIC_OK (0) or a negative pic_status and
+ *    stores a message retrievable with pic_last_error().  No exception or
+ *    abort crosses the ABI.
+ *  - Memory: bulk arrays (particle store, field, outputs, scratch) are owned by
+ *    the caller and passed as device pointers; the library borrows them until
+ *    they are re-bound or the context is destroyed.  Host pointers are read
+ *    during the call only.  The library owns only metadata, mesh tables and a
+ *    repacked copy of the velocity field (device memory it allocates at set-up
+ *    calls, never in pic_advance / pic_population / pic_interpolate).
+ *  - Asynchrony: compute calls enqueue on the context's HIP stream and return
+ *    immediately.  Calls that return host values (pic_mesh_info, pic_q2_nodes,
+ *    pic_stats_read, pic_current_buffer's count) synchronise that stream.
+ *  - Layout: arrays are structure-of-arrays, component-major.  A "[d][cap]"
+ *    array stores component a of particle i at a*cap + i.
+ *  - Cells of a uniform mesh are numbered i + n0*(j + n1*k); Q2 nodes of a
+ *    structured mesh form the (2n0+1) x (2n1+1) [x (2n2+1)] grid, node (a,b,c)
+ *    at index a + (2n0+1)*(b + (2n1+1)*c).  Octree leaves keep the caller's
+ *    order; octree Q2 nodes are the distinct points of all leaves' 3x3x3 node
+ *    lattices numbered in ascending x + M*(y + M*z) order of their coordinates
+ *    on the lattice of half-finest cells (M = 2^(max_level+1) + 1).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PIC_API __attribute__((visibility("default")))
+#else
+#define PIC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,      /* bad argument */
+    PIC_ENOMEM = -2,      /* device allocation failed */
+    PIC_EDEVICE = -3,     /* HIP runtime error */
+    PIC_ESTATE = -4,      /* call out of order (e.g. advance before bind) */
+    PIC_ECAPACITY = -5,   /* store capacity too small; pic_stats.live holds the need */
+    PIC_ENONFINITE = -6   /* non-finite velocity DOFs */
+} pic_status;
+
+typedef enum { PIC_EULER = 1, PIC_RK2 = 2, PIC_RK4 = 4 } pic_scheme;
+typedef enum { PIC_F64 = 0, PIC_F32 = 1 } pic_prec;
+typedef enum { PIC_INTERP_CELL_AVERAGE = 0, PIC_INTERP_LINEAR_LS = 1 } pic_interp;
+typedef enum { PIC_PROP_GIVEN = 0, PIC_PROP_INITIAL_POSITION = 1 } pic_prop_init;
+
+/* Marker for a lost particle in key arrays. */
+#define PIC_LOST 0xFFFFFFFFu
+
+/*
+ * Particle store (Sec. 2.1: id, location, reference location, N_properties
+ * scalars; N_properties is a run-time constant).  Two equally sized buffers,
+ * A (index 0) and B (index 1): each step reads the current buffer and writes
+ * the other one, sorted by cell.  cell_start[b] has n_cells+1 entries; the
+ * particles of cell K in buffer b are [cell_start[b][K], cell_start[b][K+1]),
+ * and the live count is cell_start[b][n_cells].  All pointers are device
+ * pointers owned by the caller.
+ */
+typedef struct {
+    int64_t capacity;          /* particles per buffer */
+    double *x[2];              /* [dim][capacity] locations */
+    double *xr[2];             /* [dim][capacity] reference locations in [0,1]^dim */
+    int32_t *cell[2];          /* [capacity] owning cell */
+    uint32_t *id[2];           /* [capacity] particle ids */
+    void *prop[2];             /* [n_prop][capacity], float or double per prop_prec */
+    int32_t *cell_start[2];    /* [n_cells + 1] */
+    int32_t n_prop;            /* 0..64 */
+    int32_t prop_prec;         /* pic_prec */
+    void *scratch;             /* device workspace of pic_scratch_bytes() bytes */
+    int64_t scratch_bytes;
+} pic_store;
+
+/* Counters accumulated on the device since the last pic_stats_reset(). */
+typedef struct {
+    int64_t live;         /* live particles in the current buffer */
+    int64_t lost;         /* removed because a stage or end point left the domain (Sec. 2.4, option 3) */
+    int64_t moved;        /* particles that changed cell in a step */
+    int64_t near_face;    /* particles within 1e-10 of a face in reference coordinates (or of the boundary) */
+    int64_t first_try;    /* movers found in the first neighbour searched (Sec. 2.4, search order) */
+    int64_t fallback;     /* locations that needed the global search */
+    int64_t newton_fail;  /* inverse-map evaluations that did not converge */
+    int64_t added;        /* population management: particles created (Sec. 2.5) */
+    int64_t deleted;      /* population management: particles removed */
+    int64_t steps;        /* time steps taken */
+    int64_t particle_steps; /* sum over steps of the particles advanced */
+} pic_stats;
+
+/* ---- context --------------------------------------------------------- */
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+PIC_API pic_status pic_create(pic_ctx **out, int device, void *hip_stream);
+/* Change the stream later calls enqueue on. */
+PIC_API pic_status pic_set_stream(pic_ctx *ctx, void *hip_stream);
+/* Release library-owned memory; caller buffers are untouched.  Accepts NULL. */
+PIC_API void pic_destroy(pic_ctx *ctx);
+/* Message of the last failing call on ctx; valid until the next call. */
+PIC_API const char *pic_last_error(const pic_ctx *ctx);
+
+/* ---- mesh (Sec. 2.1 data structures; Sec. 2.5 adaptive meshes) -------- */
+/* Uniform box mesh: dim 2 or 3, n[i] cells per axis on [lo, hi]. */
+PIC_API pic_status pic_mesh_uniform(pic_ctx *ctx, int dim, const int32_t n[3], const double lo[3], const double hi[3]);
+/* Move the vertices of the uniform mesh set up before: vertices is a host array
+ * [dim][n_vertices] of the (n0+1) x (n1+1) [x (n2+1)] grid, x fastest.  Cells
+ * become bi/trilinear; location uses Newton inversion of the cell map plus the
+ * vertex-neighbour search of Sec. 2.4 and a search over all cells as the
+ * last resort.  Boundary vertices must stay on the box faces. */
+PIC_API pic_status pic_mesh_displace(pic_ctx *ctx, const double *vertices);
+/* 2:1-balanced octree on the box [lo, hi]: leaf K has refinement level
+ * level[K] (<= max_level <= 10) and lower corner anchor[a*n_leaves + K] in units
+ * of the finest cell.  Host arrays.  Leaves must tile the box. */
+PIC_API pic_status pic_mesh_octree(pic_ctx *ctx, const double lo[3], const double hi[3], int max_level,
+                           int64_t n_leaves, const uint8_t *level, const int32_t *anchor);
+/* Dimension, number of cells and of Q2 nodes of the current mesh. */
+PIC_API pic_status pic_mesh_info(pic_ctx *ctx, int32_t *dim, int64_t *n_cells, int64_t *n_nodes);
+/* Coordinates of the Q2 nodes (host [dim][n_nodes]) and, if non-NULL, a host
+ * byte per node that is 1 for hanging nodes (octree only). */
+PIC_API pic_status pic_q2_nodes(pic_ctx *ctx, double *xyz, uint8_t *is_hanging);
+
+/* ---- field (Sec. 2.3: the velocity is a finite element field) ----------- */
+/* Nodal Q2 velocity U, device [dim][n_nodes] in precision `prec`.  The library
+ * copies it into its own layout (so U may be freed or changed afterwards) and,
+ * on an octree, replaces hanging-node values by the constraining coarse
+ * leaf's interpolant, coarse levels first.  Returns PIC_ENONFINITE if any
+ * value is NaN or infinite. */
+PIC_API pic_status pic_set_velocity(pic_ctx *ctx, const void *U, int prec);
+
+/* ---- store ------------------------------------------------------------ */
+/* Bytes of device scratch a store of `capacity` particles needs. */
+PIC_API pic_status pic_scratch_bytes(pic_ctx *ctx, int64_t capacity, int64_t *bytes);
+/* Bind the caller's store (copied by value; arrays borrowed).  Buffer A
+ * becomes current and empty.  Requires a mesh. */
+PIC_API pic_status pic_bind_store(pic_ctx *ctx, const pic_store *store);
+/* Index (0 = A, 1 = B) of the buffer holding the current particles. */
+PIC_API pic_status pic_current_buffer(pic_ctx *ctx, int32_t *which);
+
+/* ---- generation (Sec. 2.2) --------------------------------------------- */
+/* Reference-local generation (remark on local generation): counts[K]
+ * particles in cell K (device int32 [n_cells]), listed cell by cell in xr
+ * (device [dim][n], reference coordinates in [0,1]^dim) with ids (device
+ * uint32 [n]).  Location x = Phi_K(xr).  Properties: PIC_PROP_GIVEN copies
+ * prop_in (device [n_prop][n], store precision); PIC_PROP_INITIAL_POSITION sets
+ * property j to coordinate j mod dim of x.  Replaces the current contents. */
+PIC_API pic_status pic_seed_reference(pic_ctx *ctx, const int32_t *counts, const double *xr, const uint32_t *ids,
+                              int64_t n, int32_t prop_init, const void *prop_in);
+/* Prescribed locations (Sec. 2.2, prescribed particle locations): locate each
+ * x (device [dim][n]) in the mesh, drop points outside the domain, and store
+ * the rest sorted by (cell, input order).  Properties as above. */
+PIC_API pic_status pic_seed_positions(pic_ctx *ctx, const double *x, const uint32_t *ids, int64_t n,
+                              int32_t prop_init, const void *prop_in);
+
+/* ---- the hot path (Sec. 2.3 advection, Sec. 2.4 transport) -------------- */
+/* n_steps time steps of size dt: per step every particle is advanced with the
+ * scheme (Euler; RK2 explicit midpoint; classical RK4), every stage point and
+ * the end point are located (inverse map + neighbour search), particles whose
+ * stage or end point leaves the closed domain are removed, and the store is
+ * re-sorted stably by (new cell, moved): in each cell the particles that stayed
+ * keep their order and arrivals follow in their previous order.  eval_prec
+ * selects the arithmetic of the field evaluation (locations stay double). */
+PIC_API pic_status pic_advance(pic_ctx *ctx, double dt, int32_t n_steps, int32_t scheme, int32_t eval_prec);
+
+/* ---- population management (Sec. 2.5, Sec. 2.6) ----------------------- */
+/* Per cell: more than max_pc particles -> delete the ones with the largest
+ * ids; fewer than min_pc -> append min_pc - n particles at reference
+ * coordinates u = SplitMix64-hash(seed, step, cell, slot, axis) in [0,1),
+ * ids next_id + (exclusive scan of additions over cells) + slot, properties =
+ * mean of the cell's remaining particles, or the initial-position function if
+ * the cell is empty.  next_id starts at 1 + the largest seeded id. */
+PIC_API pic_status pic_population(pic_ctx *ctx, int32_t min_pc, int32_t max_pc, uint64_t seed, uint64_t step);
+
+/* ---- particle -> cell transfer (Sec. 2.7) ------------------------------ */
+/* PIC_INTERP_CELL_AVERAGE: out [n_cells][n_prop] arithmetic means (NaN for
+ * empty cells), aux unused.  PIC_INTERP_LINEAR_LS: per cell and property the
+ * least-squares fit c0 + sum_i c_i (xr_i - xbar_i) in reference coordinates
+ * centred at the cell's mean xbar; out [n_cells][n_prop][dim+1] = (c0, c),
+ * aux [n_cells][dim] = xbar; constant fit when the cell has fewer than dim+1
+ * particles or sigma_min/sigma_max of the design matrix is below 1e-10.
+ * count [n_cells] receives the particle counts.  Device pointers, double. */
+PIC_API pic_status pic_interpolate(pic_ctx *ctx, int32_t kind, double *out, double *aux, int32_t *count);
+
+/* ---- adjoint (derivative of the multi-step map w.r.t. the field) -------- */
+/* Bytes of device workspace for pic_advance_checkpointed with these sizes. */
+PIC_API pic_status pic_adjoint_workspace_bytes(pic_ctx *ctx, int32_t n_steps, int32_t ckpt_every, int64_t *bytes);
+/* Like pic_advance (F64 evaluation), also saving the store every ckpt_every
+ * steps into workspace (device, pic_adjoint_workspace_bytes bytes). */
+PIC_API pic_status pic_advance_checkpointed(pic_ctx *ctx, double dt, int32_t n_steps, int32_t scheme,
+                                    int32_t ckpt_every, void *workspace);
+/* Given dL/dx of the final locations (device [dim][capacity], in the order of
+ * the current buffer after pic_advance_checkpointed), accumulate dL/dU into
+ * dU (device double [dim][n_nodes]) by re-running each checkpoint segment and
+ * sweeping its RK stages in reverse.  Leaves the store as it was. */
+PIC_API pic_status pic_adjoint(pic_ctx *ctx, const double *dl_dx, void *workspace, double *dU);
+
+/* ---- statistics and profiling ------------------------------------------ */
+/* Read the counters (synchronises the stream). */
+PIC_API pic_status pic_stats_read(pic_ctx *ctx, pic_stats *out);
+/* Zero the counters (enqueued). */
+PIC_API pic_status pic_stats_reset(pic_ctx *ctx);
+/* Record a HIP event pair around every kernel launch when enable != 0. */
+PIC_API pic_status pic_profile_enable(pic_ctx *ctx, int32_t enable);
+/* Sum of kernel durations (ms) and launch count of the named kernel since
+ * profiling was enabled (synchronises).  Unknown name -> PIC_EINVAL. */
+PIC_API pic_status pic_profile_read(pic_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* ---- batched problems --------------------------------------------------- */
+typedef struct pic_batch pic_batch;
+/* Group n independent problems (each a context with mesh, field and bound,
+ * seeded store on the same device) so that their time steps run as shared
+ * launches over a work list of (problem, cell tile) items, replayed from one
+ * HIP graph.  tile_cells[0..3] gives the cells per work item for
+ * (2D RK2, 2D RK4, 3D RK2, 3D RK4); 0 = default.  The problems' streams are
+ * not used; the batch enqueues on `hip_stream`. */
+PIC_API pic_status pic_batch_create(pic_batch **out, int32_t n, pic_ctx *const *problems, const int32_t tile_cells[4],
+                            void *hip_stream);
+/* n_steps steps of every problem with its own dt / scheme (F64 evaluation). */
+PIC_API pic_status pic_batch_advance(pic_batch *b, const double *dt, const int32_t *scheme, int32_t n_steps);
+PIC_API void pic_batch_destroy(pic_batch *b);
+PIC_API const char *pic_batch_last_error(const pic_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

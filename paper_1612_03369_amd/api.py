@@ -1,0 +1,303 @@
+"""Python front end of the C ABI: one ``Problem`` = one ``pic_ctx``.
+
+Torch provides the device memory (the particle store, scratch, outputs) and
+the stream; every computation happens in the HIP library.  This module only
+allocates tensors, passes their pointers and shapes, and wraps results as
+tensor views.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class StoreTensors:
+    capacity: int
+    x: list
+    xr: list
+    cell: list
+    id: list
+    prop: list
+    cell_start: list
+    scratch: object
+    n_prop: int
+    prop_dtype: object
+
+
+class Problem:
+    """A mesh + Q2 velocity field + particle store on one GPU."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the particle library runs only on a HIP device")
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        L.check(self.lib.pic_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        self.store = None
+        self.dim = self.n_cells = self.n_nodes = None
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, status):
+        L.check(status, ctx=self.h)
+
+    # ------------------------------------------------------------------ mesh
+    def _info(self):
+        d = C.c_int32()
+        nc = C.c_int64()
+        nn = C.c_int64()
+        self._chk(self.lib.pic_mesh_info(self.h, C.byref(d), C.byref(nc), C.byref(nn)))
+        self.dim, self.n_cells, self.n_nodes = d.value, nc.value, nn.value
+
+    def mesh_uniform(self, dim, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+        n3 = np.array(list(n) + [1] * (3 - len(n)), np.int32)[:3]
+        lo3 = np.array(list(lo) + [0.0] * (3 - len(lo)), np.float64)[:3]
+        hi3 = np.array(list(hi) + [1.0] * (3 - len(hi)), np.float64)[:3]
+        self._chk(self.lib.pic_mesh_uniform(self.h, dim, _np_ptr(n3), _np_ptr(lo3), _np_ptr(hi3)))
+        self._info()
+
+    def mesh_displace(self, vertices):
+        v = np.ascontiguousarray(vertices, np.float64)
+        self._chk(self.lib.pic_mesh_displace(self.h, _np_ptr(v)))
+        self._info()
+
+    def mesh_octree(self, level, anchor, max_level, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+        lv = np.ascontiguousarray(level, np.uint8)
+        an = np.ascontiguousarray(anchor, np.int32)
+        lo3 = np.array(lo, np.float64)
+        hi3 = np.array(hi, np.float64)
+        self._chk(self.lib.pic_mesh_octree(self.h, _np_ptr(lo3), _np_ptr(hi3), int(max_level), lv.shape[0],
+                                           _np_ptr(lv), _np_ptr(an)))
+        self._info()
+
+    def q2_nodes(self):
+        xyz = np.zeros((self.dim, self.n_nodes), np.float64)
+        hang = np.zeros(self.n_nodes, np.uint8)
+        self._chk(self.lib.pic_q2_nodes(self.h, _np_ptr(xyz), _np_ptr(hang)))
+        return xyz, hang.astype(bool)
+
+    # ----------------------------------------------------------------- field
+    def set_velocity(self, U):
+        """U: [dim][n_nodes] float64 or float32 (numpy or torch); copied by the library."""
+        torch = _torch()
+        t = torch.as_tensor(U).to(self.device).contiguous()
+        if t.dtype not in (torch.float64, torch.float32):
+            t = t.to(torch.float64)
+        if tuple(t.shape) != (self.dim, self.n_nodes):
+            raise ValueError(f"U must have shape ({self.dim}, {self.n_nodes})")
+        prec = L.PIC_F64 if t.dtype == torch.float64 else L.PIC_F32
+        self._chk(self.lib.pic_set_velocity(self.h, _ptr(t), prec))
+
+    # ----------------------------------------------------------------- store
+    def allocate(self, capacity: int, n_prop: int = 0, prop_dtype="float64"):
+        torch = _torch()
+        dev = self.device
+        pd = torch.float64 if str(prop_dtype).endswith("64") else torch.float32
+        sb = C.c_int64()
+        self._chk(self.lib.pic_scratch_bytes(self.h, int(capacity), C.byref(sb)))
+        d = self.dim
+        st = StoreTensors(
+            capacity=int(capacity),
+            x=[torch.zeros((d, capacity), dtype=torch.float64, device=dev) for _ in range(2)],
+            xr=[torch.zeros((d, capacity), dtype=torch.float64, device=dev) for _ in range(2)],
+            cell=[torch.zeros(capacity, dtype=torch.int32, device=dev) for _ in range(2)],
+            id=[torch.zeros(capacity, dtype=torch.int32, device=dev) for _ in range(2)],
+            prop=[torch.zeros((max(n_prop, 1), capacity), dtype=pd, device=dev) for _ in range(2)],
+            cell_start=[torch.zeros(self.n_cells + 1, dtype=torch.int32, device=dev) for _ in range(2)],
+            scratch=torch.zeros(int(sb.value), dtype=torch.uint8, device=dev),
+            n_prop=int(n_prop), prop_dtype=pd)
+        s = L.PicStore()
+        s.capacity = int(capacity)
+        for b in range(2):
+            s.x[b] = st.x[b].data_ptr()
+            s.xr[b] = st.xr[b].data_ptr()
+            s.cell[b] = st.cell[b].data_ptr()
+            s.id[b] = st.id[b].data_ptr()
+            s.prop[b] = st.prop[b].data_ptr()
+            s.cell_start[b] = st.cell_start[b].data_ptr()
+        s.n_prop = int(n_prop)
+        s.prop_prec = L.PIC_F64 if pd == torch.float64 else L.PIC_F32
+        s.scratch = st.scratch.data_ptr()
+        s.scratch_bytes = int(sb.value)
+        self._chk(self.lib.pic_bind_store(self.h, C.byref(s)))
+        self.store = st
+        self._cstore = s
+        return st
+
+    def seed_reference(self, counts, xr, ids, prop=None, init_position=True):
+        torch = _torch()
+        dev = self.device
+        c = torch.as_tensor(np.ascontiguousarray(counts, np.int32)).to(dev)
+        x = torch.as_tensor(np.ascontiguousarray(xr, np.float64)).to(dev).contiguous()
+        i = torch.as_tensor(np.ascontiguousarray(ids, np.uint32).view(np.int32)).to(dev)
+        n = x.shape[1]
+        p = None
+        if prop is not None:
+            p = torch.as_tensor(prop).to(dev).to(self.store.prop_dtype).contiguous()
+        mode = L.PIC_PROP_INITIAL_POSITION if (init_position and prop is None) else L.PIC_PROP_GIVEN
+        self._chk(self.lib.pic_seed_reference(self.h, _ptr(c), _ptr(x), _ptr(i), n, mode, _ptr(p)))
+
+    def seed_positions(self, x, ids, prop=None, init_position=True):
+        torch = _torch()
+        dev = self.device
+        xt = torch.as_tensor(np.ascontiguousarray(x, np.float64)).to(dev).contiguous()
+        i = torch.as_tensor(np.ascontiguousarray(ids, np.uint32).view(np.int32)).to(dev)
+        p = None
+        if prop is not None:
+            p = torch.as_tensor(prop).to(dev).to(self.store.prop_dtype).contiguous()
+        mode = L.PIC_PROP_INITIAL_POSITION if (init_position and prop is None) else L.PIC_PROP_GIVEN
+        self._chk(self.lib.pic_seed_positions(self.h, _ptr(xt), _ptr(i), xt.shape[1], mode, _ptr(p)))
+
+    def current_index(self) -> int:
+        w = C.c_int32()
+        self._chk(self.lib.pic_current_buffer(self.h, C.byref(w)))
+        return w.value
+
+    def current(self, copy=True):
+        """Current buffer as tensors sliced to the live count (synchronises)."""
+        b = self.current_index()
+        st = self.store
+        cs = st.cell_start[b]
+        n = int(cs[-1].item())
+        out = dict(x=st.x[b][:, :n], xr=st.xr[b][:, :n], cell=st.cell[b][:n], id=st.id[b][:n],
+                   prop=st.prop[b][: st.n_prop, :n], cell_start=cs, n=n, buffer=b)
+        if copy:
+            out = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in out.items()}
+        return out
+
+    def numpy(self):
+        cur = self.current(copy=False)
+        out = {}
+        for k, v in cur.items():
+            if hasattr(v, "cpu"):
+                a = v.cpu().numpy()
+                if k == "id":
+                    a = a.view(np.uint32)
+                out[k] = a
+            else:
+                out[k] = v
+        return out
+
+    # -------------------------------------------------------------- hot path
+    def advance(self, dt, n_steps=1, scheme=L.PIC_RK4, eval_prec=L.PIC_F64):
+        self._chk(self.lib.pic_advance(self.h, float(dt), int(n_steps), int(scheme), int(eval_prec)))
+
+    def population(self, pmin, pmax, seed, step):
+        self._chk(self.lib.pic_population(self.h, int(pmin), int(pmax), int(seed), int(step)))
+
+    def interpolate(self, kind=L.PIC_INTERP_CELL_AVERAGE):
+        torch = _torch()
+        dev = self.device
+        npr = self.store.n_prop
+        cnt = torch.zeros(self.n_cells, dtype=torch.int32, device=dev)
+        if kind == L.PIC_INTERP_CELL_AVERAGE:
+            out = torch.zeros((self.n_cells, npr), dtype=torch.float64, device=dev)
+            self._chk(self.lib.pic_interpolate(self.h, kind, _ptr(out), None, _ptr(cnt)))
+            return out, None, cnt
+        out = torch.zeros((self.n_cells, npr, self.dim + 1), dtype=torch.float64, device=dev)
+        aux = torch.zeros((self.n_cells, self.dim), dtype=torch.float64, device=dev)
+        self._chk(self.lib.pic_interpolate(self.h, kind, _ptr(out), _ptr(aux), _ptr(cnt)))
+        return out, aux, cnt
+
+    # ------------------------------------------------------------- adjoint
+    def adjoint_workspace(self, n_steps, ckpt_every):
+        torch = _torch()
+        b = C.c_int64()
+        self._chk(self.lib.pic_adjoint_workspace_bytes(self.h, int(n_steps), int(ckpt_every), C.byref(b)))
+        return torch.zeros(int(b.value), dtype=torch.uint8, device=self.device)
+
+    def advance_checkpointed(self, dt, n_steps, scheme, ckpt_every, workspace):
+        self._chk(self.lib.pic_advance_checkpointed(self.h, float(dt), int(n_steps), int(scheme), int(ckpt_every),
+                                                    _ptr(workspace)))
+
+    def adjoint(self, dl_dx_full, workspace, dU):
+        """dl_dx_full: [dim][capacity] float64 in the current buffer's order; dU accumulated."""
+        self._chk(self.lib.pic_adjoint(self.h, _ptr(dl_dx_full), _ptr(workspace), _ptr(dU)))
+
+    # --------------------------------------------------------- statistics
+    def stats(self) -> dict:
+        s = L.PicStats()
+        self._chk(self.lib.pic_stats_read(self.h, C.byref(s)))
+        return {n: getattr(s, n) for n, _ in L.PicStats._fields_}
+
+    def stats_reset(self):
+        self._chk(self.lib.pic_stats_reset(self.h))
+
+    def profile(self, enable: bool):
+        self._chk(self.lib.pic_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self, kernel: str):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._chk(self.lib.pic_profile_read(self.h, kernel.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+class Batch:
+    """Many problems stepped together from one HIP graph."""
+
+    def __init__(self, problems, tile_cells=(0, 0, 0, 0), stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.problems = list(problems)
+        # graphs cannot be captured on the legacy default stream: use a stream of our own
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=problems[0].device)
+        arr = (C.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
+        tiles = (C.c_int32 * 4)(*[int(t) for t in tile_cells])
+        h = C.c_void_p()
+        L.check(self.lib.pic_batch_create(C.byref(h), len(self.problems), arr, tiles,
+                                          C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def advance(self, dts, schemes, n_steps):
+        n = len(self.problems)
+        dt = (C.c_double * n)(*[float(v) for v in dts])
+        sc = (C.c_int32 * n)(*[int(v) for v in schemes])
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.problems[0].device)
+        self.stream.wait_stream(cur)
+        L.check(self.lib.pic_batch_advance(self.h, dt, sc, int(n_steps)), batch=self.h)
+        cur.wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.pic_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

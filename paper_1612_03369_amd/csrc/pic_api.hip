@@ -1,0 +1,891 @@
+// C ABI of the particle hot path: context, mesh set-up, store binding and
+// launch sequencing.  The kernels live in pic_kernels.hip / pic_adjoint.hip;
+// this file only prepares tables and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_kernels.hip"
+#include "pic_adjoint.hip"
+
+using namespace pic;
+
+namespace {
+
+struct ProfEvent {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct pic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // mesh
+    bool have_mesh = false;
+    MeshDev mesh{};
+    std::vector<void *> mesh_allocs;
+    std::vector<double> node_xyz;        // host copy of Q2 node coordinates
+    std::vector<uint8_t> node_hanging;
+    std::vector<std::pair<int64_t, int64_t>> hanging;   // (node, constraining leaf), coarse first
+    std::vector<int32_t> h_cell_nodes;                  // octree [n_cells][27]
+    std::vector<uint8_t> h_level;
+    std::vector<int32_t> h_anchor;
+    // field
+    void *u64 = nullptr, *u32 = nullptr;
+    bool have_field = false;
+    // store
+    bool bound = false;
+    pic_store store{};
+    ScratchDev scr{};
+    int tile = 64;
+    // device problem descriptor and work lists
+    ProblemDev h_prob{};
+    ProblemDev *d_prob = nullptr;
+    WorkItem *d_work = nullptr;
+    int n_work = 0;
+    ScanItem *d_scan = nullptr;
+    int n_scan = 0;
+    RangeItem *d_rp = nullptr;   // particle ranges over the capacity
+    int n_rp = 0;
+    RangeItem *d_rc = nullptr;   // cell ranges
+    int n_rc = 0;
+    double last_dt = std::nan("");
+    // profiling
+    bool profile = false;
+    std::vector<ProfEvent> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<double, int64_t>> prof;
+    // adjoint
+    int64_t adj_steps = 0, adj_every = 0;
+    double adj_dt = 0.0;
+    int adj_scheme = 0;
+};
+
+namespace {
+
+pic_status fail(pic_ctx *c, pic_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(c, expr)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((c), e_ == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+    } while (0)
+
+hipEvent_t take_event(pic_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// Launch with optional event pair for profiling.
+template <typename K, typename... A>
+pic_status launch(pic_ctx *c, const char *name, K kernel, unsigned grid, unsigned block, A... args)
+{
+    if (grid == 0) return PIC_OK;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (c->profile) {
+        ea = take_event(c);
+        eb = take_event(c);
+        (void)hipEventRecord(ea, c->stream);
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, args...);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, PIC_EDEVICE, "launch %s: %s", name, hipGetErrorString(e));
+    if (c->profile) {
+        (void)hipEventRecord(eb, c->stream);
+        c->pending.push_back({name, ea, eb});
+    }
+    return PIC_OK;
+}
+
+#define LAUNCH(c, name, kernel, grid, block, ...)                          \
+    do {                                                                   \
+        pic_status s_ = launch((c), (name), (kernel), (grid), (block), __VA_ARGS__); \
+        if (s_ != PIC_OK) return s_;                                       \
+    } while (0)
+
+pic_status collect_profile(pic_ctx *c)
+{
+    if (c->pending.empty()) return PIC_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        auto &slot = c->prof[p.name];
+        slot.first += ms;
+        slot.second += 1;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return PIC_OK;
+}
+
+template <typename T> pic_status dalloc(pic_ctx *c, T **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    HIPCHK(c, hipMalloc((void **)p, n * sizeof(T)));
+    return PIC_OK;
+}
+
+template <typename T> pic_status mesh_upload(pic_ctx *c, const T *host, size_t n, const T **dev)
+{
+    T *d = nullptr;
+    pic_status s = dalloc(c, &d, n);
+    if (s) return s;
+    c->mesh_allocs.push_back(d);
+    HIPCHK(c, hipMemcpy(d, host, n * sizeof(T), hipMemcpyHostToDevice));
+    *dev = d;
+    return PIC_OK;
+}
+
+void free_mesh(pic_ctx *c)
+{
+    for (void *p : c->mesh_allocs) hipFree(p);
+    c->mesh_allocs.clear();
+    if (c->u64) hipFree(c->u64);
+    if (c->u32) hipFree(c->u32);
+    c->u64 = c->u32 = nullptr;
+    c->have_mesh = false;
+    c->node_xyz.clear();
+    c->node_hanging.clear();
+    c->hanging.clear();
+    c->h_cell_nodes.clear();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t n_chunks(int64_t nc) { return (nc + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+
+// Layout of the caller's scratch buffer.
+size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    char *key = take(4 * (size_t)cap);
+    char *slot = take(4 * (size_t)cap);
+    char *src = take(4 * (size_t)cap);
+    char *stay = take(4 * (size_t)nc);
+    char *arr = take(4 * (size_t)nc);
+    char *cur = take(4 * (size_t)(nc + 1));
+    char *chk = take(8 * (size_t)(n_chunks(nc) + 1));
+    char *st = take(8 * ST_COUNT);
+    char *nid = take(8);
+    char *fl = take(16);
+    if (s) {
+        s->key = (uint32_t *)key;
+        s->slot = (uint32_t *)slot;
+        s->src = (int32_t *)src;
+        s->n_stay = (int32_t *)stay;
+        s->n_arrive = (int32_t *)arr;
+        s->cursor = (int32_t *)cur;
+        s->chunk = (int64_t *)chk;
+        s->stats = (unsigned long long *)st;
+        s->next_id = (unsigned long long *)nid;
+        s->flags = (int32_t *)fl;
+    }
+    return off;
+}
+
+// Derived mesh quantities shared by all kinds.
+void mesh_common(MeshDev &m)
+{
+    double hmin[3];
+    for (int a = 0; a < 3; ++a) {
+        m.h[a] = (m.hi[a] - m.lo[a]) / (m.n[a] > 0 ? m.n[a] : 1);
+        m.inv_h[a] = 1.0 / m.h[a];
+        hmin[a] = m.kind == MESH_OCTREE ? m.fine_h[a] : m.h[a];
+    }
+    for (int a = 0; a < 3; ++a) m.bnd_tol[a] = NEAR_TOL * hmin[a];
+}
+
+pic_status upload_problem(pic_ctx *c)
+{
+    if (!c->d_prob) {
+        pic_status s = dalloc(c, &c->d_prob, 1);
+        if (s) return s;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_prob, &c->h_prob, sizeof(ProblemDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+// Work lists for one problem.
+pic_status build_work(pic_ctx *c)
+{
+    const int64_t nc = c->mesh.n_cells;
+    const int64_t cap = c->store.capacity;
+    std::vector<WorkItem> w;
+    for (int64_t k = 0; k < nc; k += c->tile) w.push_back({0, (int32_t)k, (int32_t)std::min<int64_t>(nc, k + c->tile)});
+    std::vector<ScanItem> sc;
+    for (int64_t k = 0; k < n_chunks(nc); ++k) sc.push_back({0, (int32_t)k});
+    std::vector<RangeItem> rp, rc;
+    for (int64_t k = 0; k < cap; k += BLOCK) rp.push_back({0, 0, k, std::min<int64_t>(cap, k + BLOCK)});
+    for (int64_t k = 0; k < nc; k += BLOCK) rc.push_back({0, 0, k, std::min<int64_t>(nc, k + BLOCK)});
+    for (void *p : {(void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp, (void *)c->d_rc})
+        if (p) hipFree(p);
+    c->d_work = nullptr;
+    c->d_scan = nullptr;
+    c->d_rp = nullptr;
+    c->d_rc = nullptr;
+    pic_status s;
+    if ((s = dalloc(c, &c->d_work, w.size()))) return s;
+    if ((s = dalloc(c, &c->d_scan, sc.size()))) return s;
+    if ((s = dalloc(c, &c->d_rp, rp.size()))) return s;
+    if ((s = dalloc(c, &c->d_rc, rc.size()))) return s;
+    HIPCHK(c, hipMemcpy(c->d_work, w.data(), w.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_scan, sc.data(), sc.size() * sizeof(ScanItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_rp, rp.data(), rp.size() * sizeof(RangeItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_rc, rc.data(), rc.size() * sizeof(RangeItem), hipMemcpyHostToDevice));
+    c->n_work = (int)w.size();
+    c->n_scan = (int)sc.size();
+    c->n_rp = (int)rp.size();
+    c->n_rc = (int)rc.size();
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel dispatch over (dim, scheme, precision, mesh kind)
+// ---------------------------------------------------------------------------
+using AdvectFn = void (*)(const ProblemDev *, const WorkItem *, int);
+
+template <int D, int S, typename T> AdvectFn advect_for_kind(int kind)
+{
+    switch (kind) {
+    case MESH_UNIFORM: return k_advect<D, S, T, MESH_UNIFORM>;
+    case MESH_DISPLACED: return k_advect<D, S, T, MESH_DISPLACED>;
+    default:
+        if constexpr (D == 3) return k_advect<D, S, T, MESH_OCTREE>;
+        return nullptr;
+    }
+}
+template <int D, int S> AdvectFn advect_for_prec(int prec, int kind)
+{
+    return prec == PIC_F32 ? advect_for_kind<D, S, float>(kind) : advect_for_kind<D, S, double>(kind);
+}
+template <int D> AdvectFn advect_for_scheme(int scheme, int prec, int kind)
+{
+    switch (scheme) {
+    case PIC_EULER: return advect_for_prec<D, 1>(prec, kind);
+    case PIC_RK2: return advect_for_prec<D, 2>(prec, kind);
+    case PIC_RK4: return advect_for_prec<D, 4>(prec, kind);
+    }
+    return nullptr;
+}
+AdvectFn advect_kernel(int dim, int scheme, int prec, int kind)
+{
+    return dim == 2 ? advect_for_scheme<2>(scheme, prec, kind) : advect_for_scheme<3>(scheme, prec, kind);
+}
+
+pic_status require_ready(pic_ctx *c, bool field)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
+    if (field && !c->have_field) return fail(c, PIC_ESTATE, "no velocity field");
+    return PIC_OK;
+}
+
+pic_status set_dt(pic_ctx *c, double dt)
+{
+    if (dt == c->last_dt) return PIC_OK;
+    c->last_dt = dt;
+    c->h_prob.dt = dt;
+    HIPCHK(c, hipMemcpyAsync(&c->d_prob->dt, &c->h_prob.dt, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+// scan (mode 0: stayers + arrivals, 1: population packed, 2: n_arrive only)
+pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode)
+{
+    LAUNCH(c, "scan_reduce", k_scan_reduce, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
+    LAUNCH(c, "scan_top", k_scan_top, 1u, BLOCK, (const ProblemDev *)dp, 1);
+    LAUNCH(c, "scan_down", k_scan_down, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
+    return PIC_OK;
+}
+
+// place + fix + gather + flip after the counts are in n_stay / n_arrive
+pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step)
+{
+    pic_status s = enqueue_scan(c, dp, 0);
+    if (s) return s;
+    LAUNCH(c, "place", k_place, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+    LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+    LAUNCH(c, "gather", k_gather, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+    LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, count_step);
+    return PIC_OK;
+}
+
+pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
+{
+    AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind);
+    if (!f) return fail(c, PIC_EINVAL, "unsupported combination dim=%d scheme=%d kind=%d", c->mesh.dim, scheme, c->mesh.kind);
+    LAUNCH(c, "advect", f, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+    return enqueue_sort(c, dp, 1);
+}
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+extern "C" pic_status pic_create(pic_ctx **out, int device, void *stream)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PIC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return PIC_EDEVICE;
+    pic_ctx *c = new pic_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_stream(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return PIC_OK;
+}
+
+extern "C" void pic_destroy(pic_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    free_mesh(c);
+    for (void *p : {c->u64, c->u32, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
+                    (void *)c->d_rc})
+        if (p) hipFree(p);
+    for (auto &p : c->pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) hipEventDestroy(e);
+    delete c;
+}
+
+extern "C" const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+// ===========================================================================
+// meshes
+// ===========================================================================
+extern "C" pic_status pic_mesh_uniform(pic_ctx *c, int dim, const int32_t n[3], const double lo[3], const double hi[3])
+{
+    if (!c) return PIC_EINVAL;
+    if (dim != 2 && dim != 3) return fail(c, PIC_EINVAL, "dim must be 2 or 3");
+    if (!n || !lo || !hi) return fail(c, PIC_EINVAL, "null argument");
+    int64_t nc = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (n[a] < 1) return fail(c, PIC_EINVAL, "n[%d] < 1", a);
+        if (!(hi[a] > lo[a])) return fail(c, PIC_EINVAL, "hi[%d] <= lo[%d]", a, a);
+        nc *= n[a];
+    }
+    if (nc >= (int64_t)INT32_MAX) return fail(c, PIC_EINVAL, "too many cells");
+    hipSetDevice(c->device);
+    free_mesh(c);
+    MeshDev m{};
+    m.dim = dim;
+    m.kind = MESH_UNIFORM;
+    for (int a = 0; a < 3; ++a) {
+        m.n[a] = a < dim ? n[a] : 1;
+        m.lo[a] = a < dim ? lo[a] : 0.0;
+        m.hi[a] = a < dim ? hi[a] : 1.0;
+    }
+    m.nnx = 2 * m.n[0] + 1;
+    m.nny = 2 * m.n[1] + 1;
+    m.nvx = m.n[0] + 1;
+    m.nvy = m.n[1] + 1;
+    m.n_cells = nc;
+    m.n_nodes = (int64_t)m.nnx * m.nny * (dim == 3 ? 2 * m.n[2] + 1 : 1);
+    m.n_vert = (int64_t)m.nvx * m.nvy * (dim == 3 ? m.n[2] + 1 : 1);
+    mesh_common(m);
+    c->mesh = m;
+    // host node coordinates
+    c->node_xyz.assign((size_t)dim * m.n_nodes, 0.0);
+    for (int64_t g = 0; g < m.n_nodes; ++g) {
+        int64_t a = g % m.nnx, b = (g / m.nnx) % m.nny, cc = g / ((int64_t)m.nnx * m.nny);
+        int64_t ii[3] = {a, b, cc};
+        for (int q = 0; q < dim; ++q) c->node_xyz[q * m.n_nodes + g] = m.lo[q] + 0.5 * (double)ii[q] * m.h[q];
+    }
+    c->have_mesh = true;
+    c->have_field = false;
+    c->bound = false;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_mesh_displace(pic_ctx *c, const double *vertices)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh || c->mesh.kind != MESH_UNIFORM) return fail(c, PIC_ESTATE, "displace needs a uniform mesh first");
+    if (!vertices) return fail(c, PIC_EINVAL, "null vertices");
+    MeshDev &m = c->mesh;
+    const int d = m.dim;
+    // boundary vertices must stay on their faces
+    for (int64_t g = 0; g < m.n_vert; ++g) {
+        int64_t ii[3] = {g % m.nvx, (g / m.nvx) % m.nvy, g / ((int64_t)m.nvx * m.nvy)};
+        for (int a = 0; a < d; ++a) {
+            double v = vertices[a * m.n_vert + g];
+            if (!std::isfinite(v)) return fail(c, PIC_EINVAL, "non-finite vertex");
+            if (ii[a] == 0 && v != m.lo[a]) return fail(c, PIC_EINVAL, "boundary vertex %lld left face lo[%d]", (long long)g, a);
+            if (ii[a] == m.n[a] && v != m.hi[a]) return fail(c, PIC_EINVAL, "boundary vertex %lld left face hi[%d]", (long long)g, a);
+        }
+    }
+    hipSetDevice(c->device);
+    pic_status s = mesh_upload(c, vertices, (size_t)d * m.n_vert, &m.vert);
+    if (s) return s;
+    m.kind = MESH_DISPLACED;
+    // node coordinates: Phi_K of the node's reference point
+    std::vector<double> X(8 * 3);
+    for (int64_t K = 0; K < m.n_cells; ++K) {
+        int ijk[3] = {(int)(K % m.n[0]), (int)((K / m.n[0]) % m.n[1]), d == 3 ? (int)(K / ((int64_t)m.n[0] * m.n[1])) : 0};
+        for (int v = 0; v < (1 << d); ++v) {
+            int64_t g = (ijk[0] + (v & 1)) + (int64_t)m.nvx * ((ijk[1] + ((v >> 1) & 1)) + (int64_t)m.nvy * (ijk[2] + ((v >> 2) & 1)));
+            for (int a = 0; a < d; ++a) X[v * 3 + a] = vertices[a * m.n_vert + g];
+        }
+        for (int loc = 0; loc < (d == 3 ? 27 : 9); ++loc) {
+            int la = loc % 3, lb = (loc / 3) % 3, lc = loc / 9;
+            double t[3] = {0.5 * la, 0.5 * lb, 0.5 * lc};
+            int64_t g = (2 * ijk[0] + la) + (int64_t)m.nnx * ((2 * ijk[1] + lb) + (int64_t)m.nny * (2 * ijk[2] + lc));
+            for (int a = 0; a < d; ++a) {
+                double x = 0.0;
+                for (int v = 0; v < (1 << d); ++v) {
+                    double N = 1.0;
+                    for (int q = 0; q < d; ++q) N *= ((v >> q) & 1) ? t[q] : 1.0 - t[q];
+                    x += N * X[v * 3 + a];
+                }
+                c->node_xyz[a * m.n_nodes + g] = x;
+            }
+        }
+    }
+    if (c->bound) {
+        c->h_prob.mesh = m;
+        s = upload_problem(c);
+        if (s) return s;
+    }
+    c->have_field = false;
+    return PIC_OK;
+}
+
+#include "pic_octree.inc"
+
+extern "C" pic_status pic_mesh_info(pic_ctx *c, int32_t *dim, int64_t *n_cells, int64_t *n_nodes)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (dim) *dim = c->mesh.dim;
+    if (n_cells) *n_cells = c->mesh.n_cells;
+    if (n_nodes) *n_nodes = c->mesh.n_nodes;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_q2_nodes(pic_ctx *c, double *xyz, uint8_t *is_hanging)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (xyz) std::memcpy(xyz, c->node_xyz.data(), c->node_xyz.size() * sizeof(double));
+    if (is_hanging) {
+        if (c->node_hanging.empty()) std::memset(is_hanging, 0, (size_t)c->mesh.n_nodes);
+        else std::memcpy(is_hanging, c->node_hanging.data(), c->node_hanging.size());
+    }
+    return PIC_OK;
+}
+
+// ===========================================================================
+// field
+// ===========================================================================
+extern "C" pic_status pic_set_velocity(pic_ctx *c, const void *U, int prec)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (!U) return fail(c, PIC_EINVAL, "null field");
+    if (prec != PIC_F64 && prec != PIC_F32) return fail(c, PIC_EINVAL, "bad precision");
+    hipSetDevice(c->device);
+    const int d = c->mesh.dim;
+    const int64_t nn = c->mesh.n_nodes;
+    const size_t w = d == 3 ? 4 : 2;
+    if (!c->u64) {
+        pic_status s;
+        if ((s = dalloc(c, (double **)&c->u64, w * (size_t)nn))) return s;
+        if ((s = dalloc(c, (float **)&c->u32, w * (size_t)nn))) return s;
+    }
+    int *flag = nullptr;
+    pic_status s = dalloc(c, &flag, 1);
+    if (s) return s;
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    unsigned grid = (unsigned)((nn + BLOCK - 1) / BLOCK);
+    if (d == 3)
+        hipLaunchKernelGGL(k_repack_field<3>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, c->u64, c->u32, flag);
+    else
+        hipLaunchKernelGGL(k_repack_field<2>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, c->u64, c->u32, flag);
+    int hflag = 0;
+    HIPCHK(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipFree(flag);
+    if (hflag) return fail(c, PIC_ENONFINITE, "velocity has NaN or infinite values");
+    if (c->mesh.kind == MESH_OCTREE) {
+        s = resolve_hanging(c);
+        if (s) return s;
+    }
+    c->have_field = true;
+    c->h_prob.u64 = c->u64;
+    c->h_prob.u32 = c->u32;
+    if (c->bound) return upload_problem(c);
+    return PIC_OK;
+}
+
+// ===========================================================================
+// store
+// ===========================================================================
+extern "C" pic_status pic_scratch_bytes(pic_ctx *c, int64_t capacity, int64_t *bytes)
+{
+    if (!c || !bytes) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (capacity < 0) return fail(c, PIC_EINVAL, "negative capacity");
+    *bytes = (int64_t)scratch_layout(capacity, c->mesh.n_cells, nullptr, nullptr);
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
+{
+    if (!c || !s) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    if (s->capacity < 1 || s->capacity >= (int64_t)INT32_MAX) return fail(c, PIC_EINVAL, "capacity out of range");
+    if (s->n_prop < 0 || s->n_prop > 64) return fail(c, PIC_EINVAL, "n_prop out of range");
+    if (s->prop_prec != PIC_F64 && s->prop_prec != PIC_F32) return fail(c, PIC_EINVAL, "bad prop precision");
+    for (int b = 0; b < 2; ++b)
+        if (!s->x[b] || !s->xr[b] || !s->cell[b] || !s->id[b] || !s->cell_start[b] || (s->n_prop && !s->prop[b]))
+            return fail(c, PIC_EINVAL, "null store array in buffer %d", b);
+    int64_t need = (int64_t)scratch_layout(s->capacity, c->mesh.n_cells, nullptr, nullptr);
+    if (!s->scratch || s->scratch_bytes < need) return fail(c, PIC_EINVAL, "scratch too small: need %lld bytes", (long long)need);
+    hipSetDevice(c->device);
+    c->store = *s;
+    scratch_layout(s->capacity, c->mesh.n_cells, (char *)s->scratch, &c->scr);
+    ProblemDev &P = c->h_prob;
+    P = ProblemDev{};
+    P.mesh = c->mesh;
+    for (int b = 0; b < 2; ++b) P.store[b] = StoreDev{s->x[b], s->xr[b], s->cell[b], s->id[b], s->prop[b], s->cell_start[b]};
+    P.cur = 0;
+    P.n_prop = s->n_prop;
+    P.prop_f64 = s->prop_prec == PIC_F64;
+    P.cap = s->capacity;
+    P.dt = 0.0;
+    P.u64 = c->u64;
+    P.u32 = c->u32;
+    P.scr = c->scr;
+    c->last_dt = 0.0;
+    // zeroed state: empty buffers, zero counters
+    const int64_t nc = c->mesh.n_cells;
+    HIPCHK(c, hipMemsetAsync(s->cell_start[0], 0, sizeof(int32_t) * (nc + 1), c->stream));
+    HIPCHK(c, hipMemsetAsync(s->cell_start[1], 0, sizeof(int32_t) * (nc + 1), c->stream));
+    HIPCHK(c, hipMemsetAsync(s->scratch, 0, (size_t)need, c->stream));
+    pic_status st = upload_problem(c);
+    if (st) return st;
+    c->bound = true;
+    return build_work(c);
+}
+
+extern "C" pic_status pic_current_buffer(pic_ctx *c, int32_t *which)
+{
+    if (!c || !which) return PIC_EINVAL;
+    if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
+    int v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, &c->d_prob->cur, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *which = v;
+    return PIC_OK;
+}
+
+// ===========================================================================
+// generation
+// ===========================================================================
+namespace {
+template <int D>
+pic_status seed_ref_launch(pic_ctx *c, const double *xr, const uint32_t *ids, int64_t n, int pi, const void *pin)
+{
+    unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM:
+        LAUNCH(c, "seed", (k_seed_reference<D, MESH_UNIFORM>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+        break;
+    case MESH_DISPLACED:
+        LAUNCH(c, "seed", (k_seed_reference<D, MESH_DISPLACED>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+        break;
+    default:
+        if constexpr (D == 3) LAUNCH(c, "seed", (k_seed_reference<D, MESH_OCTREE>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+    }
+    return PIC_OK;
+}
+template <int D>
+pic_status seed_pos_launch(pic_ctx *c, const double *x, const uint32_t *ids, int64_t n, int pi, const void *pin)
+{
+    unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM:
+        LAUNCH(c, "seed_positions", (k_seed_positions<D, MESH_UNIFORM>), grid, BLOCK, c->d_prob, 0, x, ids, n, pi, pin);
+        break;
+    case MESH_DISPLACED:
+        LAUNCH(c, "seed_positions", (k_seed_positions<D, MESH_DISPLACED>), grid, BLOCK, c->d_prob, 0, x, ids, n, pi, pin);
+        break;
+    default:
+        if constexpr (D == 3)
+            LAUNCH(c, "seed_positions", (k_seed_positions<D, MESH_OCTREE>), grid, BLOCK, c->d_prob, 0, x, ids, n, pi, pin);
+    }
+    return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_seed_reference(pic_ctx *c, const int32_t *counts, const double *xr, const uint32_t *ids, int64_t n,
+                                         int32_t prop_init, const void *prop_in)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (!counts || (n > 0 && (!xr || !ids))) return fail(c, PIC_EINVAL, "null argument");
+    if (n < 0 || n > c->store.capacity) return fail(c, PIC_ECAPACITY, "n=%lld exceeds capacity %lld", (long long)n, (long long)c->store.capacity);
+    if (prop_init != PIC_PROP_GIVEN && prop_init != PIC_PROP_INITIAL_POSITION) return fail(c, PIC_EINVAL, "bad prop_init");
+    if (prop_init == PIC_PROP_GIVEN && c->store.n_prop > 0 && n > 0 && !prop_in) return fail(c, PIC_EINVAL, "null prop_in");
+    hipSetDevice(c->device);
+    // cell_start of the current buffer = exclusive scan of counts; check the total
+    std::vector<int32_t> h(c->mesh.n_cells);
+    HIPCHK(c, hipMemcpyAsync(h.data(), counts, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> cs(h.size() + 1, 0);
+    int64_t run = 0;
+    for (size_t k = 0; k < h.size(); ++k) {
+        if (h[k] < 0) return fail(c, PIC_EINVAL, "negative count");
+        cs[k] = (int32_t)run;
+        run += h[k];
+    }
+    cs[h.size()] = (int32_t)run;
+    if (run != n) return fail(c, PIC_EINVAL, "sum of counts %lld != n %lld", (long long)run, (long long)n);
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(c, &cur))) return s;
+    HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur], cs.data(), sizeof(int32_t) * cs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8, c->stream));
+    s = c->mesh.dim == 2 ? seed_ref_launch<2>(c, xr, ids, n, prop_init, prop_in) : seed_ref_launch<3>(c, xr, ids, n, prop_init, prop_in);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint32_t *ids, int64_t n, int32_t prop_init,
+                                         const void *prop_in)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (n < 0 || n > c->store.capacity) return fail(c, PIC_ECAPACITY, "n exceeds capacity");
+    if (n > 0 && (!x || !ids)) return fail(c, PIC_EINVAL, "null argument");
+    if (prop_init == PIC_PROP_GIVEN && c->store.n_prop > 0 && n > 0 && !prop_in) return fail(c, PIC_EINVAL, "null prop_in");
+    hipSetDevice(c->device);
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(c, &cur))) return s;
+    const int64_t nc = c->mesh.n_cells;
+    // every point is an "arrival": no stayers; live count of the unsorted input = n
+    HIPCHK(c, hipMemsetAsync(c->scr.n_stay, 0, sizeof(int32_t) * nc, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.n_arrive, 0, sizeof(int32_t) * nc, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.cursor, 0, sizeof(int32_t) * (nc + 1), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8, c->stream));
+    int32_t n32 = (int32_t)n;
+    HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur] + nc, &n32, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    s = c->mesh.dim == 2 ? seed_pos_launch<2>(c, x, ids, n, prop_init, prop_in) : seed_pos_launch<3>(c, x, ids, n, prop_init, prop_in);
+    if (s) return s;
+    s = enqueue_sort(c, c->d_prob, 0);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+// ===========================================================================
+// advance
+// ===========================================================================
+extern "C" pic_status pic_advance(pic_ctx *c, double dt, int32_t n_steps, int32_t scheme, int32_t eval_prec)
+{
+    pic_status s = require_ready(c, true);
+    if (s) return s;
+    if (!(std::isfinite(dt)) || dt < 0.0) return fail(c, PIC_EINVAL, "dt must be finite and >= 0");
+    if (n_steps < 0) return fail(c, PIC_EINVAL, "n_steps < 0");
+    if (scheme != PIC_EULER && scheme != PIC_RK2 && scheme != PIC_RK4) return fail(c, PIC_EINVAL, "bad scheme");
+    if (eval_prec != PIC_F64 && eval_prec != PIC_F32) return fail(c, PIC_EINVAL, "bad eval precision");
+    if (c->mesh.kind == MESH_OCTREE && c->mesh.dim != 3) return fail(c, PIC_EINVAL, "octree is 3D");
+    hipSetDevice(c->device);
+    if ((s = set_dt(c, dt))) return s;
+    for (int k = 0; k < n_steps; ++k)
+        if ((s = enqueue_step(c, c->d_prob, scheme, eval_prec))) return s;
+    return PIC_OK;
+}
+
+// ===========================================================================
+// population management
+// ===========================================================================
+extern "C" pic_status pic_population(pic_ctx *c, int32_t min_pc, int32_t max_pc, uint64_t seed, uint64_t step)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (min_pc < 0 || max_pc < 1 || min_pc > max_pc) return fail(c, PIC_EINVAL, "need 0 <= min <= max, max >= 1");
+    hipSetDevice(c->device);
+    // total after the clamp must fit: computed exactly by the scan, checked here
+    if (c->h_prob.pop_min != min_pc || c->h_prob.pop_max != max_pc) {
+        c->h_prob.pop_min = min_pc;
+        c->h_prob.pop_max = max_pc;
+        int32_t mm[2] = {min_pc, max_pc};
+        HIPCHK(c, hipMemcpyAsync(&c->d_prob->pop_min, mm, sizeof(mm), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if ((s = enqueue_scan(c, c->d_prob, 1))) return s;
+    // capacity check needs the total: read it (population is not a graph-captured call)
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(c, &cur))) return s;
+    int32_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, c->store.cell_start[1 - cur] + c->mesh.n_cells, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((int64_t)total > c->store.capacity) return fail(c, PIC_ECAPACITY, "population needs capacity %d", total);
+    unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM:
+        if (c->mesh.dim == 2) LAUNCH(c, "population", (k_population<2, MESH_UNIFORM>), grid, BLOCK, (const ProblemDev *)c->d_prob, 0, seed, step);
+        else LAUNCH(c, "population", (k_population<3, MESH_UNIFORM>), grid, BLOCK, (const ProblemDev *)c->d_prob, 0, seed, step);
+        break;
+    case MESH_DISPLACED:
+        if (c->mesh.dim == 2) LAUNCH(c, "population", (k_population<2, MESH_DISPLACED>), grid, BLOCK, (const ProblemDev *)c->d_prob, 0, seed, step);
+        else LAUNCH(c, "population", (k_population<3, MESH_DISPLACED>), grid, BLOCK, (const ProblemDev *)c->d_prob, 0, seed, step);
+        break;
+    default:
+        LAUNCH(c, "population", (k_population<3, MESH_OCTREE>), grid, BLOCK, (const ProblemDev *)c->d_prob, 0, seed, step);
+    }
+    LAUNCH(c, "population_finish", k_population_finish, 1u, 1u, c->d_prob, 0);
+    return PIC_OK;
+}
+
+// ===========================================================================
+// interpolation
+// ===========================================================================
+extern "C" pic_status pic_interpolate(pic_ctx *c, int32_t kind, double *out, double *aux, int32_t *count)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (!out || !count) return fail(c, PIC_EINVAL, "null output");
+    hipSetDevice(c->device);
+    unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
+    if (kind == PIC_INTERP_CELL_AVERAGE) {
+        LAUNCH(c, "interp_average", k_interp_average, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, count);
+    } else if (kind == PIC_INTERP_LINEAR_LS) {
+        if (!aux) return fail(c, PIC_EINVAL, "linear least squares needs aux (xbar)");
+        if (c->mesh.dim == 2) LAUNCH(c, "interp_lls", k_interp_lls<2>, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, aux, count);
+        else LAUNCH(c, "interp_lls", k_interp_lls<3>, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, aux, count);
+    } else {
+        return fail(c, PIC_EINVAL, "unknown interpolation kind %d", kind);
+    }
+    return PIC_OK;
+}
+
+// ===========================================================================
+// statistics and profiling
+// ===========================================================================
+extern "C" pic_status pic_stats_read(pic_ctx *c, pic_stats *out)
+{
+    if (!c || !out) return PIC_EINVAL;
+    if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
+    hipSetDevice(c->device);
+    unsigned long long st[ST_COUNT];
+    HIPCHK(c, hipMemcpyAsync(st, c->scr.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    int32_t cur = 0;
+    pic_status s = pic_current_buffer(c, &cur);
+    if (s) return s;
+    int32_t live = 0;
+    HIPCHK(c, hipMemcpyAsync(&live, c->store.cell_start[cur] + c->mesh.n_cells, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out->live = live;
+    out->lost = (int64_t)st[ST_LOST];
+    out->moved = (int64_t)st[ST_MOVED];
+    out->near_face = (int64_t)st[ST_NEAR];
+    out->first_try = (int64_t)st[ST_FIRST_TRY];
+    out->fallback = (int64_t)st[ST_FALLBACK];
+    out->newton_fail = (int64_t)st[ST_NEWTON_FAIL];
+    out->added = (int64_t)st[ST_ADDED];
+    out->deleted = (int64_t)st[ST_DELETED];
+    out->steps = (int64_t)st[ST_STEPS];
+    out->particle_steps = (int64_t)st[ST_PSTEPS];
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_stats_reset(pic_ctx *c)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
+    hipSetDevice(c->device);
+    HIPCHK(c, hipMemsetAsync(c->scr.stats, 0, sizeof(unsigned long long) * ST_COUNT, c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_profile_enable(pic_ctx *c, int32_t enable)
+{
+    if (!c) return PIC_EINVAL;
+    pic_status s = collect_profile(c);
+    if (s) return s;
+    c->profile = enable != 0;
+    if (enable) c->prof.clear();
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_profile_read(pic_ctx *c, const char *kernel, double *total_ms, int64_t *launches)
+{
+    if (!c || !kernel) return PIC_EINVAL;
+    pic_status s = collect_profile(c);
+    if (s) return s;
+    auto it = c->prof.find(kernel);
+    if (it == c->prof.end()) {
+        if (total_ms) *total_ms = 0.0;
+        if (launches) *launches = 0;
+        static const char *known[] = {"advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip",
+                                      "seed", "seed_positions", "population", "population_finish", "interp_average",
+                                      "interp_lls", "adjoint_step", "adjoint_save", "batch_advect"};
+        for (const char *k : known)
+            if (!std::strcmp(k, kernel)) return PIC_OK;
+        return fail(c, PIC_EINVAL, "unknown kernel name %s", kernel);
+    }
+    if (total_ms) *total_ms = it->second.first;
+    if (launches) *launches = it->second.second;
+    return PIC_OK;
+}
+
+#include "pic_adjoint_api.inc"
+#include "pic_batch.inc"

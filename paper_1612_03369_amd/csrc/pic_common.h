@@ -1,0 +1,669 @@
+// Device-side types and helpers of the particle hot path (gfx950).
+//
+// Q2 field evaluation (Sec. 2.3: the velocity is evaluated through the shape
+// functions on the reference cell at the stored reference location), the
+// cell maps Phi_K and their inverses, and point location (Sec. 2.4: in-cell
+// test via xhat in Khat, vertex-neighbour search ordered by a.b, global
+// search as the last resort).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr uint32_t LOST = 0xFFFFFFFFu;
+constexpr double NEAR_TOL = 1e-10;   // near-face band in reference coordinates
+constexpr int BLOCK = 256;           // threads per workgroup of the per-tile kernels
+constexpr int MAX_TILE = 1024;       // cells per work item (LDS arrays are sized by it)
+constexpr int MAX_NBR = 64;          // vertex neighbours of one cell (octree upper bound)
+
+enum MeshKind : int { MESH_UNIFORM = 0, MESH_DISPLACED = 1, MESH_OCTREE = 2 };
+
+// Counter slots in the device statistics array.
+enum StatSlot : int {
+    ST_LOST = 0, ST_MOVED, ST_NEAR, ST_FIRST_TRY, ST_FALLBACK, ST_NEWTON_FAIL, ST_ADDED, ST_DELETED,
+    ST_STEPS, ST_SEARCHED, ST_PSTEPS, ST_COUNT = 16
+};
+
+struct MeshDev {
+    int dim, kind;
+    int n[3];                 // structured: cells per axis
+    int nnx, nny;             // structured Q2 node grid extents 2n+1
+    int nvx, nvy;             // structured vertex grid extents n+1
+    int64_t n_cells, n_nodes, n_vert;
+    double lo[3], hi[3], h[3], inv_h[3];
+    double bnd_tol[3];        // near-boundary band per axis (1e-10 * smallest cell edge)
+    const double *vert;       // displaced: [dim][n_vert]
+    // octree
+    int max_level;
+    double fine_h[3], inv_fine_h[3];
+    const int32_t *anchor;    // [3][n_cells] finest-cell units
+    const uint8_t *level;     // [n_cells]
+    const int32_t *fine;      // [(2^L)^3] finest cell -> leaf
+    const int32_t *cell_nodes;// [n_cells][27]
+    // vertex-neighbour lists (displaced, octree)
+    const int32_t *nbr_off;   // [n_cells + 1]
+    const int32_t *nbr;       // [nbr_off[n_cells]]
+};
+
+// One buffer of the particle store.
+struct StoreDev {
+    double *x;       // [dim][cap]
+    double *xr;      // [dim][cap]
+    int32_t *cell;   // [cap]
+    uint32_t *id;    // [cap]
+    void *prop;      // [n_prop][cap]
+    int32_t *cs;     // [n_cells + 1]
+};
+
+// Per-context scratch (carved out of the caller's workspace).
+struct ScratchDev {
+    uint32_t *key;        // [cap] new cell or LOST
+    uint32_t *slot;       // [cap] rank of a stayer within its cell
+    int32_t *src;         // [cap] gather source of each destination slot
+    int32_t *n_stay;      // [nc]
+    int32_t *n_arrive;    // [nc]
+    int32_t *cursor;      // [nc]
+    int64_t *chunk;       // [n_chunks + 1]
+    unsigned long long *stats;  // [ST_COUNT]
+    unsigned long long *next_id;// [1]
+    int32_t *flags;       // [4]
+};
+
+// ---------------------------------------------------------------------------
+// node value vectors: 3D fields padded to 4 components, 2D to 2
+// ---------------------------------------------------------------------------
+template <int D, typename T> struct NodeVec;
+template <> struct NodeVec<3, float> { using type = float4; };
+template <> struct NodeVec<3, double> { using type = double4; };
+template <> struct NodeVec<2, float> { using type = float2; };
+template <> struct NodeVec<2, double> { using type = double2; };
+
+template <typename V> __device__ __forceinline__ auto nv_x(const V &v) { return v.x; }
+template <typename V> __device__ __forceinline__ auto nv_y(const V &v) { return v.y; }
+__device__ __forceinline__ float nv_z(const float4 &v) { return v.z; }
+__device__ __forceinline__ double nv_z(const double4 &v) { return v.z; }
+__device__ __forceinline__ float nv_z(const float2 &) { return 0.f; }
+__device__ __forceinline__ double nv_z(const double2 &) { return 0.0; }
+
+// ---------------------------------------------------------------------------
+// 1D quadratic Lagrange basis on the nodes {0, 1/2, 1} and its derivative
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ void lag3(T t, T l[3])
+{
+    l[0] = (T(1) - t) * (T(1) - T(2) * t);
+    l[1] = T(4) * t * (T(1) - t);
+    l[2] = t * (T(2) * t - T(1));
+}
+template <typename T> __device__ __forceinline__ void dlag3(T t, T d[3])
+{
+    d[0] = T(4) * t - T(3);
+    d[1] = T(4) - T(8) * t;
+    d[2] = T(4) * t - T(1);
+}
+
+// Node index of local node (0,0,0) of structured cell K and its (i,j,k).
+__device__ __forceinline__ void cell_ijk(const MeshDev &m, int64_t K, int ijk[3])
+{
+    ijk[0] = (int)(K % m.n[0]);
+    ijk[1] = (int)((K / m.n[0]) % m.n[1]);
+    ijk[2] = m.dim == 3 ? (int)(K / ((int64_t)m.n[0] * m.n[1])) : 0;
+}
+
+// Global node of local node (a,b,c) in cell K.
+template <int D, int KIND>
+__device__ __forceinline__ int64_t q2_node(const MeshDev &m, int64_t K, int a, int b, int c)
+{
+    if constexpr (KIND == MESH_OCTREE) {
+        return m.cell_nodes[K * 27 + a + 3 * b + 9 * c];
+    } else {
+        int ijk[3];
+        cell_ijk(m, K, ijk);
+        return (2 * ijk[0] + a) + (int64_t)m.nnx * ((2 * ijk[1] + b) + (int64_t)m.nny * (2 * ijk[2] + c));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Q2 evaluation, sum-factorised: u = sum_c lc sum_b lb sum_a la U[a,b,c]
+// ---------------------------------------------------------------------------
+template <int D, typename T, int KIND>
+__device__ __forceinline__ void eval_q2(const MeshDev &m, const typename NodeVec<D, T>::type *__restrict__ U,
+                                        int64_t K, const double *tr, double *u)
+{
+    T t0 = (T)tr[0], t1 = (T)tr[1];
+    T la[3], lb[3];
+    lag3(t0, la);
+    lag3(t1, lb);
+    if constexpr (D == 2) {
+        T a0 = 0, a1 = 0;
+        if constexpr (KIND == MESH_OCTREE) {
+            // not used: octree meshes are 3D
+        } else {
+            int ijk[3];
+            cell_ijk(m, K, ijk);
+            const auto *base = U + (2 * ijk[0]) + (int64_t)m.nnx * (2 * ijk[1]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const auto *row = base + (int64_t)m.nnx * b;
+                auto v0 = row[0], v1 = row[1], v2 = row[2];
+                T s0 = la[0] * v0.x + la[1] * v1.x + la[2] * v2.x;
+                T s1 = la[0] * v0.y + la[1] * v1.y + la[2] * v2.y;
+                a0 += lb[b] * s0;
+                a1 += lb[b] * s1;
+            }
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+    } else {
+        T lc[3];
+        lag3((T)tr[2], lc);
+        T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                typename NodeVec<D, T>::type v0, v1, v2;
+                if constexpr (KIND == MESH_OCTREE) {
+                    const int32_t *cn = m.cell_nodes + K * 27 + 3 * b + 9 * c;
+                    v0 = U[cn[0]];
+                    v1 = U[cn[1]];
+                    v2 = U[cn[2]];
+                } else {
+                    int ijk[3];
+                    cell_ijk(m, K, ijk);
+                    const auto *row = U + (2 * ijk[0]) +
+                                      (int64_t)m.nnx * ((2 * ijk[1] + b) + (int64_t)m.nny * (2 * ijk[2] + c));
+                    v0 = row[0];
+                    v1 = row[1];
+                    v2 = row[2];
+                }
+                T s0 = la[0] * v0.x + la[1] * v1.x + la[2] * v2.x;
+                T s1 = la[0] * v0.y + la[1] * v1.y + la[2] * v2.y;
+                T s2 = la[0] * v0.z + la[1] * v1.z + la[2] * v2.z;
+                r0 += lb[b] * s0;
+                r1 += lb[b] * s1;
+                r2 += lb[b] * s2;
+            }
+            a0 += lc[c] * r0;
+            a1 += lc[c] * r1;
+            a2 += lc[c] * r2;
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+        u[2] = (double)a2;
+    }
+}
+
+// Reference gradient G[c][r] = d u_c / d xhat_r (double precision).
+template <int D, int KIND>
+__device__ __forceinline__ void eval_q2_refgrad(const MeshDev &m, const typename NodeVec<D, double>::type *__restrict__ U,
+                                                int64_t K, const double *tr, double G[3][3])
+{
+    double l[3][3], dl[3][3];
+    for (int a = 0; a < D; ++a) {
+        lag3(tr[a], l[a]);
+        dlag3(tr[a], dl[a]);
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) G[c][r] = 0.0;
+    const int nc = D == 3 ? 3 : 1;
+    for (int c3 = 0; c3 < nc; ++c3)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                auto v = U[q2_node<D, KIND>(m, K, a, b, c3)];
+                double w0, w1, w2 = 0.0;
+                if constexpr (D == 2) {
+                    w0 = dl[0][a] * l[1][b];
+                    w1 = l[0][a] * dl[1][b];
+                } else {
+                    w0 = dl[0][a] * l[1][b] * l[2][c3];
+                    w1 = l[0][a] * dl[1][b] * l[2][c3];
+                    w2 = l[0][a] * l[1][b] * dl[2][c3];
+                }
+                double vc[3] = {(double)nv_x(v), (double)nv_y(v), (double)nv_z(v)};
+                for (int c = 0; c < D; ++c) {
+                    G[c][0] += vc[c] * w0;
+                    G[c][1] += vc[c] * w1;
+                    if constexpr (D == 3) G[c][2] += vc[c] * w2;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// cell maps
+// ---------------------------------------------------------------------------
+// Axis-aligned box of a uniform or octree cell.
+template <int KIND>
+__device__ __forceinline__ void cell_box(const MeshDev &m, int64_t K, double x0[3], double h[3])
+{
+    if constexpr (KIND == MESH_OCTREE) {
+        int s = 1 << (m.max_level - (int)m.level[K]);
+        for (int a = 0; a < 3; ++a) {
+            x0[a] = m.lo[a] + (double)m.anchor[a * m.n_cells + K] * m.fine_h[a];
+            h[a] = (double)s * m.fine_h[a];
+        }
+    } else {
+        int ijk[3];
+        cell_ijk(m, K, ijk);
+        for (int a = 0; a < 3; ++a) {
+            x0[a] = m.lo[a] + (double)ijk[a] * m.h[a];
+            h[a] = m.h[a];
+        }
+    }
+}
+
+// Vertices of a displaced structured cell, X[v][a], v = va + 2 vb + 4 vc.
+template <int D>
+__device__ __forceinline__ void cell_vertices(const MeshDev &m, int64_t K, double X[8][3])
+{
+    int ijk[3];
+    cell_ijk(m, K, ijk);
+    for (int v = 0; v < (1 << D); ++v) {
+        int va = v & 1, vb = (v >> 1) & 1, vc = (v >> 2) & 1;
+        int64_t g = (ijk[0] + va) + (int64_t)m.nvx * ((ijk[1] + vb) + (int64_t)m.nvy * (ijk[2] + vc));
+        for (int a = 0; a < D; ++a) X[v][a] = m.vert[a * m.n_vert + g];
+    }
+}
+
+// Multilinear map and Jacobian J[a][r] of a displaced cell.
+template <int D>
+__device__ __forceinline__ void q1_map(const double X[8][3], const double *t, double *x, double J[3][3])
+{
+    for (int a = 0; a < D; ++a) {
+        x[a] = 0.0;
+        for (int r = 0; r < D; ++r) J[a][r] = 0.0;
+    }
+    for (int v = 0; v < (1 << D); ++v) {
+        double f[3], df[3];
+        for (int a = 0; a < D; ++a) {
+            int bit = (v >> a) & 1;
+            f[a] = bit ? t[a] : 1.0 - t[a];
+            df[a] = bit ? 1.0 : -1.0;
+        }
+        double N = f[0] * f[1] * (D == 3 ? f[2] : 1.0);
+        double g[3];
+        g[0] = df[0] * f[1] * (D == 3 ? f[2] : 1.0);
+        g[1] = f[0] * df[1] * (D == 3 ? f[2] : 1.0);
+        g[2] = D == 3 ? f[0] * f[1] * df[2] : 0.0;
+        for (int a = 0; a < D; ++a) {
+            x[a] += N * X[v][a];
+            for (int r = 0; r < D; ++r) J[a][r] += g[r] * X[v][a];
+        }
+    }
+}
+
+template <int D> __device__ __forceinline__ bool solve_small(const double J[3][3], const double *r, double *s)
+{
+    if constexpr (D == 2) {
+        double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        if (det == 0.0) return false;
+        double inv = 1.0 / det;
+        s[0] = (r[0] * J[1][1] - J[0][1] * r[1]) * inv;
+        s[1] = (J[0][0] * r[1] - r[0] * J[1][0]) * inv;
+        return true;
+    } else {
+        double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        if (det == 0.0) return false;
+        double inv = 1.0 / det;
+        double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        // s = J^{-1} r = adj(J) r / det, adj(J)[r][c] = cofactor[c][r]
+        s[0] = (c00 * r[0] + c10 * r[1] + c20 * r[2]) * inv;
+        s[1] = (c01 * r[0] + c11 * r[1] + c21 * r[2]) * inv;
+        s[2] = (c02 * r[0] + c12 * r[1] + c22 * r[2]) * inv;
+        return true;
+    }
+}
+
+// Phi_K(t) for any mesh kind.
+template <int D, int KIND>
+__device__ __forceinline__ void map_to_real(const MeshDev &m, int64_t K, const double *t, double *x)
+{
+    if constexpr (KIND == MESH_DISPLACED) {
+        double X[8][3], J[3][3];
+        cell_vertices<D>(m, K, X);
+        q1_map<D>(X, t, x, J);
+    } else {
+        double x0[3], h[3];
+        cell_box<KIND>(m, K, x0, h);
+        for (int a = 0; a < D; ++a) x[a] = x0[a] + t[a] * h[a];
+    }
+}
+
+// Jacobian of Phi_K at t (for gradients on displaced cells).
+template <int D, int KIND>
+__device__ __forceinline__ void map_jacobian(const MeshDev &m, int64_t K, const double *t, double J[3][3])
+{
+    if constexpr (KIND == MESH_DISPLACED) {
+        double X[8][3], x[3];
+        cell_vertices<D>(m, K, X);
+        q1_map<D>(X, t, x, J);
+    } else {
+        double x0[3], h[3];
+        cell_box<KIND>(m, K, x0, h);
+        for (int a = 0; a < 3; ++a)
+            for (int r = 0; r < 3; ++r) J[a][r] = (a == r) ? h[a] : 0.0;
+    }
+}
+
+// Inverse map: Newton from the cell centre (1 exact step on affine cells).
+template <int D, int KIND>
+__device__ __forceinline__ bool map_to_ref(const MeshDev &m, int64_t K, const double *x, double *t)
+{
+    if constexpr (KIND == MESH_DISPLACED) {
+        double X[8][3];
+        cell_vertices<D>(m, K, X);
+        for (int a = 0; a < D; ++a) t[a] = 0.5;
+        for (int it = 0; it < 12; ++it) {
+            double y[3], J[3][3], r[3], s[3];
+            q1_map<D>(X, t, y, J);
+            for (int a = 0; a < D; ++a) r[a] = y[a] - x[a];
+            if (!solve_small<D>(J, r, s)) return false;
+            double dmax = 0.0;
+            for (int a = 0; a < D; ++a) {
+                t[a] -= s[a];
+                dmax = fmax(dmax, fabs(s[a]));
+            }
+            if (dmax < 1e-14) return true;
+        }
+        return false;
+    } else {
+        double x0[3], h[3];
+        cell_box<KIND>(m, K, x0, h);
+        for (int a = 0; a < D; ++a) t[a] = (x[a] - x0[a]) / h[a];
+        return true;
+    }
+}
+
+// Is axis a of cell K on the upper face of the domain?
+template <int KIND>
+__device__ __forceinline__ bool on_upper_face(const MeshDev &m, int64_t K, int a)
+{
+    if constexpr (KIND == MESH_OCTREE) {
+        int s = 1 << (m.max_level - (int)m.level[K]);
+        return m.anchor[a * m.n_cells + K] + s == (1 << m.max_level);
+    } else {
+        int ijk[3];
+        cell_ijk(m, K, ijk);
+        return ijk[a] == m.n[a] - 1;
+    }
+}
+
+// Half-open in-cell test of reference coordinates.
+template <int D, int KIND>
+__device__ __forceinline__ bool ref_inside(const MeshDev &m, int64_t K, const double *t)
+{
+    for (int a = 0; a < D; ++a) {
+        if (!(t[a] >= 0.0)) return false;
+        if (t[a] < 1.0) continue;
+        if (t[a] == 1.0 && on_upper_face<KIND>(m, K, a)) continue;
+        return false;
+    }
+    return true;
+}
+
+template <int D> __device__ __forceinline__ double face_dist(const double *t)
+{
+    double d = fmin(t[0], 1.0 - t[0]);
+    for (int a = 1; a < D; ++a) d = fmin(d, fmin(t[a], 1.0 - t[a]));
+    return d;
+}
+
+template <int D> __device__ __forceinline__ bool in_box_domain(const MeshDev &m, const double *y)
+{
+    for (int a = 0; a < D; ++a)
+        if (!(y[a] >= m.lo[a] && y[a] <= m.hi[a])) return false;
+    return true;
+}
+
+template <int D> __device__ __forceinline__ bool near_boundary(const MeshDev &m, const double *y)
+{
+    bool nb = false;
+    for (int a = 0; a < D; ++a)
+        nb |= (int)(fabs(y[a] - m.lo[a]) < m.bnd_tol[a]) | (int)(fabs(y[a] - m.hi[a]) < m.bnd_tol[a]);
+    return nb;
+}
+
+// Location statistics gathered per thread.
+struct LocStats {
+    int first_try, fallback, newton_fail, searched;
+};
+
+// Global search of a displaced mesh: every cell whose bounding box (+1e-10)
+// holds y; first pass half-open, second pass closed with tolerance 1e-12,
+// taking the most interior candidate (ties: lowest index).
+template <int D>
+__device__ bool global_search_displaced(const MeshDev &m, const double *y, int32_t &K, double *t, LocStats &ls)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t best = -1;
+        double best_d = -1.0, bt[3] = {0, 0, 0};
+        for (int64_t c = 0; c < m.n_cells; ++c) {
+            double X[8][3];
+            cell_vertices<D>(m, c, X);
+            bool inbox = true;
+            for (int a = 0; a < D; ++a) {
+                double mn = X[0][a], mx = X[0][a];
+                for (int v = 1; v < (1 << D); ++v) {
+                    mn = fmin(mn, X[v][a]);
+                    mx = fmax(mx, X[v][a]);
+                }
+                inbox &= (y[a] >= mn - 1e-10) && (y[a] <= mx + 1e-10);
+            }
+            if (!inbox) continue;
+            double tt[3];
+            if (!map_to_ref<D, MESH_DISPLACED>(m, c, y, tt)) {
+                ls.newton_fail++;
+                continue;
+            }
+            if (pass == 0) {
+                if (ref_inside<D, MESH_DISPLACED>(m, c, tt)) {
+                    K = (int32_t)c;
+                    for (int a = 0; a < D; ++a) t[a] = tt[a];
+                    return true;
+                }
+            } else {
+                bool ok = true;
+                for (int a = 0; a < D; ++a) ok &= (tt[a] >= -1e-12) && (tt[a] <= 1.0 + 1e-12);
+                double fd = face_dist<D>(tt);
+                if (ok && fd > best_d) {
+                    best = c;
+                    best_d = fd;
+                    for (int a = 0; a < D; ++a) bt[a] = tt[a];
+                }
+            }
+        }
+        if (pass == 1 && best >= 0) {
+            K = (int32_t)best;
+            for (int a = 0; a < D; ++a) t[a] = bt[a];
+            return true;
+        }
+    }
+    return false;
+}
+
+// Octree global search: lookup on the finest-level grid.
+__device__ __forceinline__ int32_t octree_lookup(const MeshDev &m, const double *y)
+{
+    const int fine = 1 << m.max_level;
+    int64_t f[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t i = (int64_t)floor((y[a] - m.lo[a]) * m.inv_fine_h[a]);
+        f[a] = i < 0 ? 0 : (i >= fine ? fine - 1 : i);
+    }
+    return m.fine[f[0] + (int64_t)fine * (f[1] + (int64_t)fine * f[2])];
+}
+
+// Cell centre (for the a.b search order).
+template <int D, int KIND>
+__device__ __forceinline__ void cell_centre(const MeshDev &m, int64_t K, double *c)
+{
+    double t[3] = {0.5, 0.5, 0.5};
+    map_to_real<D, KIND>(m, K, t, c);
+}
+
+// Closest vertex of cell K to y.
+template <int D, int KIND>
+__device__ __forceinline__ void closest_vertex(const MeshDev &m, int64_t K, const double *y, double *v)
+{
+    double best = 1e300;
+    for (int q = 0; q < (1 << D); ++q) {
+        double t[3] = {(double)(q & 1), (double)((q >> 1) & 1), (double)((q >> 2) & 1)};
+        double p[3];
+        map_to_real<D, KIND>(m, K, t, p);
+        double d = 0.0;
+        for (int a = 0; a < D; ++a) d += (p[a] - y[a]) * (p[a] - y[a]);
+        if (d < best) {
+            best = d;
+            for (int a = 0; a < D; ++a) v[a] = p[a];
+        }
+    }
+}
+
+/*
+ * Locate y starting from cell `hint`.  Uniform meshes: closed form (the cell is
+ * floor((y - lo)/h); the result equals what the neighbour search would find
+ * since the owning cell is unique).  Displaced and octree meshes: in-cell test
+ * of the hint, then the hint's vertex neighbours in descending order of
+ * (y - v).(c_K' - v) with v the hint's vertex closest to y, then the global
+ * search.  Returns false when y is outside the closed domain.
+ */
+template <int D, int KIND>
+__device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_t hint, int32_t &K, double *t,
+                                       LocStats &ls)
+{
+    if (!in_box_domain<D>(m, y)) return false;
+    if constexpr (KIND == MESH_UNIFORM) {
+        int64_t c = 0, stride = 1;
+        for (int a = 0; a < D; ++a) {
+            double s = (y[a] - m.lo[a]) * m.inv_h[a];
+            int i = (int)floor(s);
+            i = i >= m.n[a] ? m.n[a] - 1 : (i < 0 ? 0 : i);
+            double x0 = m.lo[a] + (double)i * m.h[a];
+            t[a] = (y[a] - x0) * m.inv_h[a];
+            c += (int64_t)i * stride;
+            stride *= m.n[a];
+        }
+        K = (int32_t)c;
+        return true;
+    } else {
+        double tt[3];
+        bool conv = map_to_ref<D, KIND>(m, hint, y, tt);
+        if (!conv) ls.newton_fail++;
+        if (conv && ref_inside<D, KIND>(m, hint, tt)) {
+            K = hint;
+            for (int a = 0; a < D; ++a) t[a] = tt[a];
+            return true;
+        }
+        // vertex neighbours ordered by descending a.b
+        double v[3], av[3];
+        closest_vertex<D, KIND>(m, hint, y, v);
+        for (int a = 0; a < D; ++a) av[a] = y[a] - v[a];
+        int32_t cand[MAX_NBR];
+        double score[MAX_NBR];
+        int nc = 0;
+        if constexpr (KIND == MESH_DISPLACED) {
+            int ijk[3];
+            cell_ijk(m, hint, ijk);
+            for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        int i = ijk[0] + dx, j = ijk[1] + dy, k = ijk[2] + dz;
+                        if (i < 0 || j < 0 || k < 0 || i >= m.n[0] || j >= m.n[1] || (D == 3 && k >= m.n[2]))
+                            continue;
+                        cand[nc++] = (int32_t)(i + (int64_t)m.n[0] * (j + (int64_t)m.n[1] * k));
+                    }
+        } else {
+            int b = m.nbr_off[hint], e = m.nbr_off[hint + 1];
+            for (int q = b; q < e && nc < MAX_NBR; ++q) cand[nc++] = m.nbr[q];
+        }
+        for (int q = 0; q < nc; ++q) {
+            double c[3];
+            cell_centre<D, KIND>(m, cand[q], c);
+            double s = 0.0;
+            for (int a = 0; a < D; ++a) s += av[a] * (c[a] - v[a]);
+            score[q] = s;
+        }
+        // selection order: descending score, ties by lower index
+        for (int tried = 0; tried < nc; ++tried) {
+            int bq = -1;
+            for (int q = 0; q < nc; ++q) {
+                if (cand[q] < 0) continue;
+                if (bq < 0 || score[q] > score[bq] || (score[q] == score[bq] && cand[q] < cand[bq])) bq = q;
+            }
+            int32_t c = cand[bq];
+            cand[bq] = -1;
+            ls.searched++;
+            bool ok = map_to_ref<D, KIND>(m, c, y, tt);
+            if (!ok) {
+                ls.newton_fail++;
+                continue;
+            }
+            if (ref_inside<D, KIND>(m, c, tt)) {
+                if (tried == 0) ls.first_try++;
+                K = c;
+                for (int a = 0; a < D; ++a) t[a] = tt[a];
+                return true;
+            }
+        }
+        ls.fallback++;
+        if constexpr (KIND == MESH_OCTREE) {
+            int32_t c = octree_lookup(m, y);
+            map_to_ref<D, KIND>(m, c, y, tt);
+            K = c;
+            for (int a = 0; a < D; ++a) t[a] = tt[a];
+            return true;
+        } else {
+            return global_search_displaced<D>(m, y, K, t, ls);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workgroup helpers
+// ---------------------------------------------------------------------------
+// Exclusive scan of 0/1 flags over a 256-thread workgroup; returns the prefix
+// and the workgroup total.  s_wave must hold BLOCK/64 ints.
+__device__ __forceinline__ int block_scan_flags(int flag, int *s_wave, int &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(flag);
+    const int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wid] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        int c = s_wave[w];
+        off += (w < wid) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + pre;
+}
+
+// Sum of an int over a wavefront.
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace pic

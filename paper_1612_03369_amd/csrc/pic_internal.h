@@ -1,0 +1,42 @@
+// Structures shared by the host launcher code and the kernels.
+#pragma once
+#include "pic_common.h"
+
+namespace pic {
+
+// Everything a kernel needs about one problem; lives in device memory so that
+// the current-buffer index can be flipped by a kernel (graph replays need no
+// host involvement).
+struct ProblemDev {
+    MeshDev mesh;
+    StoreDev store[2];
+    int cur;                 // index of the current buffer
+    int n_prop, prop_f64;
+    int pop_min, pop_max;
+    int64_t cap;
+    double dt;
+    const void *u64;         // repacked field, double
+    const void *u32;         // repacked field, float
+    ScratchDev scr;
+    // adjoint: arrays of the segment being replayed
+    const double *adj_lam_in;  // [dim][cap] lambda of the next step, in that step's order
+    double *adj_lam_out;       // [dim][cap] lambda of this step, in this step's order
+    double *adj_dU;            // [dim][n_nodes]
+    const int32_t *adj_src;    // [cap] gather sources of the step
+};
+
+struct WorkItem {
+    int32_t problem;
+    int32_t c0, c1;          // cells [c0, c1)
+};
+struct ScanItem {
+    int32_t problem;
+    int32_t chunk;
+};
+struct RangeItem {
+    int32_t problem;
+    int32_t pad;
+    int64_t begin, end;      // [begin, end) in particles or cells; one workgroup of BLOCK each
+};
+
+}  // namespace pic

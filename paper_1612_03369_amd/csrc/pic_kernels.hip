@@ -1,0 +1,780 @@
+// HIP kernels of the particle hot path for gfx950.
+//
+// One time step = advect (per tile of cells) -> scan of per-cell counts ->
+// place (destination of every particle) -> fix (arrival order) -> gather
+// (permute the store into the other buffer).
+#include "pic_common.h"
+#include "pic_internal.h"
+
+namespace pic {
+
+// ===========================================================================
+// advect + locate (Sec. 2.3 and 2.4)
+// ===========================================================================
+template <int D, int S, typename T, int KIND>
+__device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename NodeVec<D, T>::type *__restrict__ U,
+                                               double dt, double *x, double *t, int32_t K, bool &near, LocStats &ls)
+{
+    double u[3], k1[3], y[3], ty[3];
+    int32_t Ky;
+    eval_q2<D, T, KIND>(m, U, K, t, u);      // stage 1: stored (K, xhat), no location needed
+#pragma unroll
+    for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
+    double xn[3];
+    if constexpr (S == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a];
+    } else if constexpr (S == 2) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        if (!locate<D, KIND>(m, y, K, Ky, ty, ls)) return LOST;
+        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
+    } else {
+        double k2[3], k3[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        if (!locate<D, KIND>(m, y, K, Ky, ty, ls)) return LOST;
+        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) k2[a] = dt * u[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k2[a];
+        near |= near_boundary<D>(m, y);
+        if (!locate<D, KIND>(m, y, Ky, Ky, ty, ls)) return LOST;
+        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) k3[a] = dt * u[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + k3[a];
+        near |= near_boundary<D>(m, y);
+        if (!locate<D, KIND>(m, y, Ky, Ky, ty, ls)) return LOST;
+        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+        const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
+    }
+    near |= near_boundary<D>(m, xn);
+    int32_t Kn;
+    double tn[3];
+    if (!locate<D, KIND>(m, xn, K, Kn, tn, ls)) return LOST;
+    near |= face_dist<D>(tn) < NEAR_TOL;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = xn[a];
+        t[a] = tn[a];
+    }
+    return (uint32_t)Kn;
+}
+
+// Accumulate per-thread counters into the device statistics (one atomic per
+// counter per workgroup).
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot, int v, int *s_red)
+{
+    int w = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(&stats[slot], (unsigned long long)w);
+}
+
+/*
+ * Work item = tile of consecutive cells [c0, c1) of one problem.  The tile's
+ * particles are contiguous in the store; they are processed in chunks of
+ * BLOCK.  For every particle: advance + locate, write the new location and
+ * reference location in place, its key (new cell or LOST), and for particles
+ * that stay in their cell their rank among the cell's stayers (prefix scan of
+ * stay flags; the rank of a cell's first particle is the base).  Per-cell
+ * stayer counts stay in LDS; arrivals are counted with global atomics.
+ */
+template <int D, int S, typename T, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_advect(const ProblemDev *__restrict__ probs, const WorkItem *__restrict__ work,
+                                                  int n_work)
+{
+    __shared__ int s_cs[MAX_TILE + 1];
+    __shared__ int s_base[MAX_TILE];
+    __shared__ int s_cnt[MAX_TILE];
+    __shared__ int s_wave[BLOCK / 64];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const WorkItem wi = work[w];
+        const ProblemDev &P = probs[wi.problem];
+        const MeshDev &m = P.mesh;
+        const auto *U = reinterpret_cast<const typename NodeVec<D, T>::type *>(
+            sizeof(T) == 4 ? P.u32 : P.u64);
+        const StoreDev cur = P.store[P.cur];
+        const int64_t cap = P.cap;
+        const double dt = P.dt;
+        const int c0 = wi.c0, nt = wi.c1 - wi.c0;
+        for (int k = threadIdx.x; k <= nt; k += BLOCK) s_cs[k] = cur.cs[c0 + k];
+        for (int k = threadIdx.x; k < nt; k += BLOCK) s_cnt[k] = 0;
+        __syncthreads();
+        const int p0 = s_cs[0], p1 = s_cs[nt];
+        int carry = 0;
+        int st_lost = 0, st_moved = 0, st_near = 0;
+        LocStats ls = {0, 0, 0, 0};
+        for (int base = p0; base < p1; base += BLOCK) {
+            const int i = base + threadIdx.x;
+            const bool active = i < p1;
+            int stay = 0, kloc = 0;
+            uint32_t key = LOST;
+            if (active) {
+                const int32_t K = cur.cell[i];
+                kloc = K - c0;
+                double x[3], t[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    x[a] = cur.x[a * cap + i];
+                    t[a] = cur.xr[a * cap + i];
+                }
+                bool near = false;
+                key = advect_one<D, S, T, KIND>(m, U, dt, x, t, K, near, ls);
+                if (key != LOST) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        cur.x[a * cap + i] = x[a];
+                        cur.xr[a * cap + i] = t[a];
+                    }
+                }
+                stay = key == (uint32_t)K;
+                st_lost += key == LOST;
+                st_moved += (key != LOST) && !stay;
+                st_near += near;
+                P.scr.key[i] = key;
+            }
+            int total;
+            const int pre = block_scan_flags(stay, s_wave, total);
+            const int Pi = carry + pre;
+            if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
+            __syncthreads();
+            if (active) {
+                if (stay) {
+                    P.scr.slot[i] = (uint32_t)(Pi - s_base[kloc]);
+                    atomicAdd(&s_cnt[kloc], 1);
+                } else if (key != LOST) {
+                    atomicAdd(&P.scr.n_arrive[key], 1);
+                }
+            }
+            carry += total;
+            __syncthreads();
+        }
+        for (int k = threadIdx.x; k < nt; k += BLOCK) P.scr.n_stay[c0 + k] = s_cnt[k];
+        flush_stats(P.scr.stats, ST_PSTEPS, threadIdx.x == 0 ? p1 - p0 : 0, nullptr);
+        flush_stats(P.scr.stats, ST_LOST, st_lost, nullptr);
+        flush_stats(P.scr.stats, ST_MOVED, st_moved, nullptr);
+        flush_stats(P.scr.stats, ST_NEAR, st_near, nullptr);
+        if constexpr (KIND != MESH_UNIFORM) {
+            flush_stats(P.scr.stats, ST_FIRST_TRY, ls.first_try, nullptr);
+            flush_stats(P.scr.stats, ST_FALLBACK, ls.fallback, nullptr);
+            flush_stats(P.scr.stats, ST_NEWTON_FAIL, ls.newton_fail, nullptr);
+            flush_stats(P.scr.stats, ST_SEARCHED, ls.searched, nullptr);
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// scan of the new per-cell counts (three phases over chunks of cells)
+// ===========================================================================
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
+
+// int64 workgroup exclusive scan; returns the prefix, sets total.
+__device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t *s_tmp, int64_t &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t n = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += n;
+    }
+    if (lane == 63) s_tmp[wid] = inc;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        int64_t c = s_tmp[w];
+        off += (w < wid) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+// count of cell K after the step (stayers + arrivals); mode 1 = population clamp
+__device__ __forceinline__ int64_t cell_value(const ProblemDev &P, int64_t K, int mode)
+{
+    if (mode == 0) return (int64_t)P.scr.n_stay[K] + (int64_t)P.scr.n_arrive[K];
+    const StoreDev cur = P.store[P.cur];
+    int64_t n = cur.cs[K + 1] - cur.cs[K];
+    int64_t keep = n > P.pop_max ? P.pop_max : n;
+    int64_t add = keep < P.pop_min ? P.pop_min - keep : 0;
+    return (keep + add) | (add << 32);      // packed: count | additions << 32
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
+                                                       int n_items, int mode)
+{
+    __shared__ int64_t s_tmp[BLOCK / 64];
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const ScanItem it = items[w];
+        const ProblemDev &P = probs[it.problem];
+        int64_t sum = 0;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            int64_t K = (int64_t)it.chunk * SCAN_CHUNK + (int64_t)k * BLOCK + threadIdx.x;
+            if (K < P.mesh.n_cells) sum += cell_value(P, K, mode);
+        }
+        int64_t total;
+        block_scan_i64(sum, s_tmp, total);
+        if (threadIdx.x == 0) P.scr.chunk[it.chunk] = total;
+    }
+}
+
+// One workgroup per problem: exclusive scan over that problem's chunk sums.
+__global__ __launch_bounds__(BLOCK) void k_scan_top(const ProblemDev *__restrict__ probs, int n_probs)
+{
+    __shared__ int64_t s_tmp[BLOCK / 64];
+    for (int p = blockIdx.x; p < n_probs; p += gridDim.x) {
+        const ProblemDev &P = probs[p];
+        const int nch = (int)((P.mesh.n_cells + SCAN_CHUNK - 1) / SCAN_CHUNK);
+        int64_t carry = 0;
+        for (int b = 0; b < nch; b += BLOCK) {
+            int c = b + threadIdx.x;
+            int64_t v = c < nch ? P.scr.chunk[c] : 0;
+            int64_t total;
+            int64_t pre = block_scan_i64(v, s_tmp, total);
+            if (c < nch) P.scr.chunk[c] = carry + pre;
+            carry += total;
+        }
+        if (threadIdx.x == 0) P.scr.chunk[nch] = carry;
+    }
+}
+
+// Local scan + chunk offset -> cell_start of the other buffer.  Mode 0 also
+// resets the arrival counters and the placement cursors for the next step.
+__global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
+                                                     int n_items, int mode)
+{
+    __shared__ int64_t s_tmp[BLOCK / 64];
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const ScanItem it = items[w];
+        const ProblemDev &P = probs[it.problem];
+        const int64_t nc = P.mesh.n_cells;
+        const StoreDev nxt = P.store[1 - P.cur];
+        int64_t v[SCAN_PER_THREAD];
+        int64_t sum = 0;
+        const int64_t K0 = (int64_t)it.chunk * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            int64_t K = K0 + k;
+            v[k] = K < nc ? cell_value(P, K, mode) : 0;
+            sum += v[k];
+        }
+        int64_t total;
+        int64_t run = block_scan_i64(sum, s_tmp, total) + P.scr.chunk[it.chunk];
+        const int64_t nch = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            int64_t K = K0 + k;
+            if (K < nc) {
+                if (mode == 0) {
+                    nxt.cs[K] = (int32_t)run;
+                    P.scr.n_arrive[K] = 0;
+                    P.scr.cursor[K] = 0;
+                } else {
+                    nxt.cs[K] = (int32_t)(run & 0xFFFFFFFFll);
+                    P.scr.cursor[K] = (int32_t)(run >> 32);     // first new-id offset of the cell
+                }
+            }
+            run += v[k];
+        }
+        if (it.chunk == nch - 1 && threadIdx.x == 0) {
+            int64_t tot = P.scr.chunk[nch];
+            nxt.cs[nc] = (int32_t)(mode == 0 ? tot : (tot & 0xFFFFFFFFll));
+            if (mode == 1) P.scr.cursor[nc] = (int32_t)(tot >> 32);
+        }
+    }
+}
+
+// ===========================================================================
+// place / fix / gather: the stable re-sort by (new cell, moved)
+// ===========================================================================
+// Destination of every particle of the current buffer.  Stayers go to
+// new_start[K] + rank; arrivals get a provisional slot after the stayers.
+__global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
+                                                 int n_items)
+{
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const RangeItem it = items[w];
+        const ProblemDev &P = probs[it.problem];
+        const StoreDev cur = P.store[P.cur];
+        const StoreDev nxt = P.store[1 - P.cur];
+        const int64_t n = cur.cs[P.mesh.n_cells];
+        const int64_t i = it.begin + threadIdx.x;
+        if (i >= n || i >= it.end) continue;
+        const uint32_t key = P.scr.key[i];
+        if (key == LOST) continue;
+        int64_t dst;
+        if (key == (uint32_t)cur.cell[i]) {
+            dst = (int64_t)nxt.cs[key] + P.scr.slot[i];
+        } else {
+            int r = atomicAdd(&P.scr.cursor[key], 1);
+            dst = (int64_t)nxt.cs[key] + P.scr.n_stay[key] + r;
+        }
+        P.scr.src[dst] = (int32_t)i;
+    }
+}
+
+// Sort each cell's arrivals by their previous position (= previous global
+// order, since the previous store was sorted by cell).
+__global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
+                                               int n_items)
+{
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const RangeItem it = items[w];
+        const ProblemDev &P = probs[it.problem];
+        const int64_t K = it.begin + threadIdx.x;
+        if (K >= it.end || K >= P.mesh.n_cells) continue;
+        const StoreDev nxt = P.store[1 - P.cur];
+        const int64_t b = (int64_t)nxt.cs[K] + P.scr.n_stay[K];
+        const int64_t e = nxt.cs[K + 1];
+        if (e - b < 2) continue;
+        int32_t *a = P.scr.src + b;
+        const int64_t n = e - b;
+        if (n <= 32) {
+            int32_t v[32];
+            for (int64_t q = 0; q < n; ++q) v[q] = a[q];
+            for (int64_t q = 1; q < n; ++q) {
+                int32_t x = v[q];
+                int64_t r = q - 1;
+                while (r >= 0 && v[r] > x) {
+                    v[r + 1] = v[r];
+                    --r;
+                }
+                v[r + 1] = x;
+            }
+            for (int64_t q = 0; q < n; ++q) a[q] = v[q];
+        } else {
+            for (int64_t q = 1; q < n; ++q) {         // rare: many arrivals in one cell
+                int32_t x = a[q];
+                int64_t r = q - 1;
+                while (r >= 0 && a[r] > x) {
+                    a[r + 1] = a[r];
+                    --r;
+                }
+                a[r + 1] = x;
+            }
+        }
+    }
+}
+
+// Permute the store into the other buffer: new[p] = old[src[p]].
+__global__ __launch_bounds__(BLOCK) void k_gather(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
+                                                  int n_items)
+{
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const RangeItem it = items[w];
+        const ProblemDev &P = probs[it.problem];
+        const StoreDev cur = P.store[P.cur];
+        const StoreDev nxt = P.store[1 - P.cur];
+        const int64_t n = nxt.cs[P.mesh.n_cells];
+        const int64_t p = it.begin + threadIdx.x;
+        if (p >= n || p >= it.end) continue;
+        const int64_t cap = P.cap;
+        const int64_t s = P.scr.src[p];
+        const int D = P.mesh.dim;
+        for (int a = 0; a < D; ++a) {
+            nxt.x[a * cap + p] = cur.x[a * cap + s];
+            nxt.xr[a * cap + p] = cur.xr[a * cap + s];
+        }
+        nxt.id[p] = cur.id[s];
+        nxt.cell[p] = (int32_t)P.scr.key[s];
+        if (P.prop_f64) {
+            const double *ps = (const double *)cur.prop;
+            double *pd = (double *)nxt.prop;
+            for (int j = 0; j < P.n_prop; ++j) pd[j * cap + p] = ps[j * cap + s];
+        } else {
+            const float *ps = (const float *)cur.prop;
+            float *pd = (float *)nxt.prop;
+            for (int j = 0; j < P.n_prop; ++j) pd[j * cap + p] = ps[j * cap + s];
+        }
+    }
+}
+
+// Flip the current buffer of every problem and count the step.
+__global__ void k_flip(ProblemDev *probs, int n_probs, int count_step)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_probs) {
+        probs[p].cur = 1 - probs[p].cur;
+        if (count_step) atomicAdd(&probs[p].scr.stats[ST_STEPS], 1ull);
+    }
+}
+
+// ===========================================================================
+// generation (Sec. 2.2)
+// ===========================================================================
+// Reference-local generation: particle p of cell K at x = Phi_K(xr).
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int prob, const double *__restrict__ xr_in,
+                                                          const uint32_t *__restrict__ ids, int64_t n, int prop_init,
+                                                          const void *prop_in)
+{
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev cur = P.store[P.cur];
+    const int64_t cap = P.cap;
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    // owning cell: last K with cs[K] <= p
+    int64_t lo = 0, hi = m.n_cells;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (cur.cs[mid] <= p) lo = mid; else hi = mid;
+    }
+    const int64_t K = lo;
+    double t[3], x[3];
+    for (int a = 0; a < D; ++a) t[a] = xr_in[a * n + p];
+    map_to_real<D, KIND>(m, K, t, x);
+    for (int a = 0; a < D; ++a) {
+        cur.x[a * cap + p] = x[a];
+        cur.xr[a * cap + p] = t[a];
+    }
+    cur.cell[p] = (int32_t)K;
+    cur.id[p] = ids[p];
+    for (int j = 0; j < P.n_prop; ++j) {
+        double v = prop_init == 1 ? x[j % D]
+                                  : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
+        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
+        else ((float *)cur.prop)[j * cap + p] = (float)v;
+    }
+    atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);
+}
+
+// Prescribed locations: locate each point with the global search and write it
+// to the current buffer unsorted; key = cell (or LOST), every point counted as
+// an arrival so that the sort machinery orders by (cell, input order).
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int prob, const double *__restrict__ x_in,
+                                                          const uint32_t *__restrict__ ids, int64_t n, int prop_init,
+                                                          const void *prop_in)
+{
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev cur = P.store[P.cur];
+    const int64_t cap = P.cap;
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    double x[3], t[3];
+    for (int a = 0; a < D; ++a) x[a] = x_in[a * n + p];
+    int32_t K = -1;
+    LocStats ls = {0, 0, 0, 0};
+    bool ok = in_box_domain<D>(m, x);
+    if (ok) {
+        if constexpr (KIND == MESH_UNIFORM) {
+            ok = locate<D, KIND>(m, x, 0, K, t, ls);
+        } else if constexpr (KIND == MESH_OCTREE) {
+            K = octree_lookup(m, x);
+            map_to_ref<D, KIND>(m, K, x, t);
+        } else {
+            ok = global_search_displaced<D>(m, x, K, t, ls);
+        }
+    }
+    for (int a = 0; a < D; ++a) {
+        cur.x[a * cap + p] = x[a];
+        cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+    }
+    cur.cell[p] = -1;
+    cur.id[p] = ids[p];
+    for (int j = 0; j < P.n_prop; ++j) {
+        double v = prop_init == 1 ? x[j % D]
+                                  : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
+        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
+        else ((float *)cur.prop)[j * cap + p] = (float)v;
+    }
+    P.scr.key[p] = ok ? (uint32_t)K : LOST;
+    if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
+    else atomicAdd(&P.scr.stats[ST_LOST], 1ull);
+    atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);
+}
+
+// ===========================================================================
+// particle -> cell transfer (Sec. 2.7)
+// ===========================================================================
+__device__ __forceinline__ double load_prop(const ProblemDev &P, const StoreDev &s, int j, int64_t i)
+{
+    return P.prop_f64 ? ((const double *)s.prop)[j * P.cap + i] : (double)((const float *)s.prop)[j * P.cap + i];
+}
+
+// One wavefront per cell: arithmetic mean of every property (NaN if empty).
+__global__ __launch_bounds__(BLOCK) void k_interp_average(const ProblemDev *__restrict__ probs, int prob,
+                                                          double *__restrict__ out, int32_t *__restrict__ count)
+{
+    const ProblemDev &P = probs[prob];
+    const StoreDev cur = P.store[P.cur];
+    const int64_t K = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (K >= P.mesh.n_cells) return;
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1];
+    if (lane == 0) count[K] = (int32_t)(e - b);
+    for (int j = 0; j < P.n_prop; ++j) {
+        double s = 0.0;
+        for (int64_t i = b + lane; i < e; i += 64) s += load_prop(P, cur, j, i);
+        s = wave_sum(s);
+        if (lane == 0) out[K * P.n_prop + j] = (e > b) ? s / (double)(e - b) : __builtin_nan("");
+    }
+}
+
+// Eigenvalues of a symmetric 3x3 matrix (trigonometric closed form).
+__device__ inline void sym3_eig(const double A[3][3], double ev[3])
+{
+    double p1 = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    double q = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+    if (p1 == 0.0) {
+        ev[0] = A[0][0];
+        ev[1] = A[1][1];
+        ev[2] = A[2][2];
+        return;
+    }
+    double p2 = (A[0][0] - q) * (A[0][0] - q) + (A[1][1] - q) * (A[1][1] - q) + (A[2][2] - q) * (A[2][2] - q) + 2.0 * p1;
+    double p = sqrt(p2 / 6.0);
+    double B[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B[i][j] = (A[i][j] - (i == j ? q : 0.0)) / p;
+    double detB = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                  B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+    double r = fmin(1.0, fmax(-1.0, detB / 2.0));
+    double phi = acos(r) / 3.0;
+    ev[0] = q + 2.0 * p * cos(phi);
+    ev[2] = q + 2.0 * p * cos(phi + 2.0943951023931954923);
+    ev[1] = 3.0 * q - ev[0] - ev[2];
+}
+
+/*
+ * One wavefront per cell: least squares c0 + c.(xr - xbar) in centred
+ * reference coordinates.  Two passes over the cell's particles (means, then
+ * centred second moments), FP64 normal equations solved by Cramer's rule;
+ * constant fit when n < dim+1 or sigma_min/sigma_max < 1e-10 (the singular
+ * values of [1 | X - xbar] are sqrt(n) and those of X - xbar).
+ */
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_interp_lls(const ProblemDev *__restrict__ probs, int prob, double *__restrict__ out,
+                                                      double *__restrict__ xbar_out, int32_t *__restrict__ count)
+{
+    const ProblemDev &P = probs[prob];
+    const StoreDev cur = P.store[P.cur];
+    const int64_t cap = P.cap;
+    const int64_t K = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (K >= P.mesh.n_cells) return;
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1], n = e - b;
+    const int np = P.n_prop;
+    double *o = out + K * np * (D + 1);
+    if (lane == 0) count[K] = (int32_t)n;
+    if (n == 0) {
+        if (lane == 0) {
+            for (int j = 0; j < np * (D + 1); ++j) o[j] = __builtin_nan("");
+            for (int a = 0; a < D; ++a) xbar_out[K * D + a] = __builtin_nan("");
+        }
+        return;
+    }
+    double xb[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+        for (int64_t i = b + lane; i < e; i += 64) s += cur.xr[a * cap + i];
+        xb[a] = wave_sum(s) / (double)n;
+    }
+    double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int r = 0; r < D; ++r)
+        for (int c = r; c < D; ++c) {
+            double s = 0.0;
+            for (int64_t i = b + lane; i < e; i += 64) s += (cur.xr[r * cap + i] - xb[r]) * (cur.xr[c * cap + i] - xb[c]);
+            s = wave_sum(s);
+            C[r][c] = C[c][r] = s;
+        }
+    bool full = n >= D + 1;
+    if (full) {
+        double ev[3];
+        if constexpr (D == 3) {
+            sym3_eig(C, ev);
+        } else {
+            double tr = C[0][0] + C[1][1], det = C[0][0] * C[1][1] - C[0][1] * C[1][0];
+            double disc = sqrt(fmax(0.0, tr * tr / 4.0 - det));
+            ev[0] = tr / 2.0 + disc;
+            ev[1] = tr / 2.0 - disc;
+            ev[2] = ev[1];
+        }
+        double emin = ev[0], emax = ev[0];
+        for (int a = 1; a < D; ++a) {
+            emin = fmin(emin, ev[a]);
+            emax = fmax(emax, ev[a]);
+        }
+        double smin = sqrt(fmax(emin, 0.0)), smax = sqrt(fmax(emax, 0.0));
+        double sn = sqrt((double)n);
+        full = fmin(sn, smin) >= 1e-10 * fmax(sn, smax);
+    }
+    for (int j = 0; j < np; ++j) {
+        double s = 0.0;
+        for (int64_t i = b + lane; i < e; i += 64) s += load_prop(P, cur, j, i);
+        double mean = wave_sum(s) / (double)n;
+        double r[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+        if (full) {
+            for (int a = 0; a < D; ++a) {
+                double q = 0.0;
+                for (int64_t i = b + lane; i < e; i += 64) q += (cur.xr[a * cap + i] - xb[a]) * (load_prop(P, cur, j, i) - mean);
+                r[a] = wave_sum(q);
+            }
+            solve_small<D>(C, r, c);
+        }
+        if (lane == 0) {
+            o[j * (D + 1)] = mean;
+            for (int a = 0; a < D; ++a) o[j * (D + 1) + 1 + a] = full ? c[a] : 0.0;
+        }
+    }
+    if (lane == 0)
+        for (int a = 0; a < D; ++a) xbar_out[K * D + a] = xb[a];
+}
+
+// ===========================================================================
+// population management (Sec. 2.5; properties of new particles Sec. 2.6)
+// ===========================================================================
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t step, uint64_t cell, uint64_t slot, uint64_t axis)
+{
+    uint64_t h = splitmix64(seed);
+    h = splitmix64(h ^ step);
+    h = splitmix64(h ^ cell);
+    h = splitmix64(h ^ slot);
+    h = splitmix64(h ^ axis);
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/*
+ * One wavefront per cell.  Keeps the cell's particles except the ones whose
+ * id is among the (n - max) largest (stable compaction by ballot), then
+ * appends min - kept new particles.  The packed scan left the new cell_start
+ * in the other buffer and each cell's first new-id offset in cursor[].
+ */
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_population(const ProblemDev *__restrict__ probs, int prob, uint64_t seed,
+                                                      uint64_t step)
+{
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev cur = P.store[P.cur];
+    const StoreDev nxt = P.store[1 - P.cur];
+    const int64_t cap = P.cap;
+    const int64_t K = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (K >= m.n_cells) return;
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1], n = e - b;
+    const int64_t del = n > P.pop_max ? n - P.pop_max : 0;
+    int64_t q = nxt.cs[K];
+    const int np = P.n_prop;
+    double psum[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // property sums of survivors (first 8 props by lanes)
+    int kept = 0;
+    for (int64_t c0 = b; c0 < e; c0 += 64) {
+        const int64_t i = c0 + lane;
+        bool keep = false;
+        if (i < e) {
+            keep = true;
+            if (del > 0) {
+                const uint32_t myid = cur.id[i];
+                int64_t larger = 0;
+                for (int64_t k = b; k < e; ++k) larger += cur.id[k] > myid;
+                keep = larger >= del;
+            }
+        }
+        const unsigned long long msk = __ballot(keep);
+        const int pre = __popcll(msk & ((1ull << lane) - 1ull));
+        if (keep) {
+            const int64_t d = q + pre;
+            for (int a = 0; a < D; ++a) {
+                nxt.x[a * cap + d] = cur.x[a * cap + i];
+                nxt.xr[a * cap + d] = cur.xr[a * cap + i];
+            }
+            nxt.id[d] = cur.id[i];
+            nxt.cell[d] = (int32_t)K;
+            for (int j = 0; j < np; ++j) {
+                double v = load_prop(P, cur, j, i);
+                if (P.prop_f64) ((double *)nxt.prop)[j * cap + d] = v;
+                else ((float *)nxt.prop)[j * cap + d] = (float)v;
+            }
+        }
+        q += __popcll(msk);
+        kept += __popcll(msk);
+    }
+    const int64_t add = kept < P.pop_min ? P.pop_min - kept : 0;
+    if (add > 0) {
+        const uint64_t id0 = P.scr.next_id[0] + (uint64_t)P.scr.cursor[K];
+        for (int64_t s0 = 0; s0 < add; s0 += 64) {
+            const int64_t s = s0 + lane;
+            if (s < add) {
+                double t[3], x[3];
+                for (int a = 0; a < D; ++a) t[a] = hash_u01(seed, step, (uint64_t)K, (uint64_t)s, (uint64_t)a);
+                map_to_real<D, KIND>(m, K, t, x);
+                const int64_t d = q + s;
+                for (int a = 0; a < D; ++a) {
+                    nxt.x[a * cap + d] = x[a];
+                    nxt.xr[a * cap + d] = t[a];
+                }
+                nxt.id[d] = (uint32_t)(id0 + (uint64_t)s);
+                nxt.cell[d] = (int32_t)K;
+            }
+        }
+        // properties: mean of the survivors (now at [nxt.cs[K], q)), or the initial position
+        const int64_t sb = nxt.cs[K];
+        for (int j = 0; j < np; ++j) {
+            double sum = 0.0;
+            for (int64_t i = sb + lane; i < q; i += 64)
+                sum += P.prop_f64 ? ((const double *)nxt.prop)[j * cap + i] : (double)((const float *)nxt.prop)[j * cap + i];
+            sum = wave_sum(sum);
+            for (int64_t s = lane; s < add; s += 64) {
+                const int64_t d = q + s;
+                double v = kept > 0 ? sum / (double)kept : nxt.x[(j % D) * cap + d];
+                if (P.prop_f64) ((double *)nxt.prop)[j * cap + d] = v;
+                else ((float *)nxt.prop)[j * cap + d] = (float)v;
+            }
+        }
+    }
+    if (lane == 0) {
+        if (del) atomicAdd(&P.scr.stats[ST_DELETED], (unsigned long long)del);
+        if (add) atomicAdd(&P.scr.stats[ST_ADDED], (unsigned long long)add);
+    }
+    (void)psum;
+}
+
+// next_id += total additions; flip buffers.
+__global__ void k_population_finish(ProblemDev *probs, int prob)
+{
+    ProblemDev &P = probs[prob];
+    P.scr.next_id[0] += (unsigned long long)(uint32_t)P.scr.cursor[P.mesh.n_cells];
+    P.cur = 1 - P.cur;
+}
+
+// Non-finite check and repacking of the nodal field into the kernels' layout.
+template <int D>
+__global__ void k_repack_field(const void *U, int src_f32, int64_t nn, void *u64, void *u32, int *flag)
+{
+    const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= nn) return;
+    double v[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) v[a] = src_f32 ? (double)((const float *)U)[a * nn + g] : ((const double *)U)[a * nn + g];
+    bool bad = false;
+    for (int a = 0; a < D; ++a) bad |= !isfinite(v[a]);
+    if (bad) atomicOr(flag, 1);
+    if constexpr (D == 3) {
+        ((double4 *)u64)[g] = make_double4(v[0], v[1], v[2], 0.0);
+        ((float4 *)u32)[g] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+    } else {
+        ((double2 *)u64)[g] = make_double2(v[0], v[1]);
+        ((float2 *)u32)[g] = make_float2((float)v[0], (float)v[1]);
+    }
+}
+
+}  // namespace pic
