@@ -169,6 +169,10 @@ PIC_API pic_status pic_seed_reference(pic_ctx *ctx, const int32_t *counts, const
 PIC_API pic_status pic_seed_positions(pic_ctx *ctx, const double *x, const uint32_t *ids, int64_t n,
                               int32_t prop_init, const void *prop_in);
 
+/* Cells per work item of the advect kernel (1..1024; default 64).  A work
+ * item is a run of consecutive cells whose particles one workgroup advances. */
+PIC_API pic_status pic_set_tile(pic_ctx *ctx, int32_t tile_cells);
+
 /* ---- the hot path (Sec. 2.3 advection, Sec. 2.4 transport) -------------- */
 /* n_steps time steps of size dt: per step every particle is advanced with the
  * scheme (Euler; RK2 explicit midpoint; classical RK4), every stage point and

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 EXPORTS = [
     "pic_create", "pic_set_stream", "pic_destroy", "pic_last_error",
     "pic_mesh_uniform", "pic_mesh_displace", "pic_mesh_octree", "pic_mesh_info", "pic_q2_nodes",
-    "pic_set_velocity", "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer",
+    "pic_set_velocity", "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
     "pic_seed_reference", "pic_seed_positions", "pic_advance", "pic_population", "pic_interpolate",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
@@ -86,6 +86,7 @@ def load(path: str | None = None):
             "pic_scratch_bytes": (S, [P, I64, P]),
             "pic_bind_store": (S, [P, C.POINTER(PicStore)]),
             "pic_current_buffer": (S, [P, P]),
+            "pic_set_tile": (S, [P, I32]),
             "pic_seed_reference": (S, [P, P, P, P, I64, I32, P]),
             "pic_seed_positions": (S, [P, P, P, I64, I32, P]),
             "pic_advance": (S, [P, D, I32, I32, I32]),

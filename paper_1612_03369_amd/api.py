@@ -180,6 +180,9 @@ class Problem:
         mode = L.PIC_PROP_INITIAL_POSITION if (init_position and prop is None) else L.PIC_PROP_GIVEN
         self._chk(self.lib.pic_seed_positions(self.h, _ptr(xt), _ptr(i), xt.shape[1], mode, _ptr(p)))
 
+    def set_tile(self, tile_cells: int):
+        self._chk(self.lib.pic_set_tile(self.h, int(tile_cells)))
+
     def current_index(self) -> int:
         w = C.c_int32()
         self._chk(self.lib.pic_current_buffer(self.h, C.byref(w)))

@@ -31,6 +31,15 @@ def command(out: str = LIB, extra=()) -> list:
             *extra, "-o", out, *[os.path.join(CSRC, s) for s in SOURCES]]
 
 
+def build_variant(out: str, defines: dict) -> str:
+    """Compile a copy of the library with -D overrides of the tuning macros."""
+    extra = [f"-D{k}={v}" for k, v in defines.items()]
+    r = subprocess.run(command(out, extra), capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr[-20000:])
+    return out
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     """Compile libpic.so; with force=False only when a source is newer."""
     if not force and os.path.exists(LIB):

@@ -197,7 +197,6 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
         return p;
     };
     char *key = take(4 * (size_t)cap);
-    char *slot = take(4 * (size_t)cap);
     char *src = take(4 * (size_t)cap);
     char *stay = take(4 * (size_t)nc);
     char *arr = take(4 * (size_t)nc);
@@ -208,7 +207,6 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
     char *fl = take(16);
     if (s) {
         s->key = (uint32_t *)key;
-        s->slot = (uint32_t *)slot;
         s->src = (int32_t *)src;
         s->n_stay = (int32_t *)stay;
         s->n_arrive = (int32_t *)arr;
@@ -339,12 +337,16 @@ pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode)
     return PIC_OK;
 }
 
-// place + fix + gather + flip after the counts are in n_stay / n_arrive
-pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step)
+// place + fix + gather + flip after the counts are in n_stay / n_arrive;
+// unsorted = the current buffer is an unsorted input (every particle arrives)
+pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorted = false)
 {
     pic_status s = enqueue_scan(c, dp, 0);
     if (s) return s;
-    LAUNCH(c, "place", k_place, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+    if (unsorted)
+        LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+    else
+        LAUNCH(c, "place", k_place, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
     LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
     LAUNCH(c, "gather", k_gather, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, count_step);
@@ -623,6 +625,15 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     return build_work(c);
 }
 
+extern "C" pic_status pic_set_tile(pic_ctx *c, int32_t tile_cells)
+{
+    if (!c) return PIC_EINVAL;
+    if (tile_cells < 1 || tile_cells > MAX_TILE) return fail(c, PIC_EINVAL, "tile must be in [1, %d]", MAX_TILE);
+    c->tile = tile_cells;
+    if (c->bound) return build_work(c);
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_current_buffer(pic_ctx *c, int32_t *which)
 {
     if (!c || !which) return PIC_EINVAL;
@@ -641,7 +652,7 @@ namespace {
 template <int D>
 pic_status seed_ref_launch(pic_ctx *c, const double *xr, const uint32_t *ids, int64_t n, int pi, const void *pin)
 {
-    unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+    unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
     switch (c->mesh.kind) {
     case MESH_UNIFORM:
         LAUNCH(c, "seed", (k_seed_reference<D, MESH_UNIFORM>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
@@ -727,7 +738,7 @@ extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint
     HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur] + nc, &n32, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     s = c->mesh.dim == 2 ? seed_pos_launch<2>(c, x, ids, n, prop_init, prop_in) : seed_pos_launch<3>(c, x, ids, n, prop_init, prop_in);
     if (s) return s;
-    s = enqueue_sort(c, c->d_prob, 0);
+    s = enqueue_sort(c, c->d_prob, 0, true);
     if (s) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;

@@ -16,6 +16,9 @@ constexpr double NEAR_TOL = 1e-10;   // near-face band in reference coordinates
 constexpr int BLOCK = 256;           // threads per workgroup of the per-tile kernels
 constexpr int MAX_TILE = 1024;       // cells per work item (LDS arrays are sized by it)
 constexpr int MAX_NBR = 64;          // vertex neighbours of one cell (octree upper bound)
+#ifndef PIC_EVAL_UNROLL
+#define PIC_EVAL_UNROLL 3               // unroll of the outermost sum-factorisation loop
+#endif
 
 enum MeshKind : int { MESH_UNIFORM = 0, MESH_DISPLACED = 1, MESH_OCTREE = 2 };
 
@@ -59,7 +62,6 @@ struct StoreDev {
 // Per-context scratch (carved out of the caller's workspace).
 struct ScratchDev {
     uint32_t *key;        // [cap] new cell or LOST
-    uint32_t *slot;       // [cap] rank of a stayer within its cell
     int32_t *src;         // [cap] gather source of each destination slot
     int32_t *n_stay;      // [nc]
     int32_t *n_arrive;    // [nc]
@@ -158,7 +160,7 @@ __device__ __forceinline__ void eval_q2(const MeshDev &m, const typename NodeVec
         T lc[3];
         lag3((T)tr[2], lc);
         T a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
+#pragma unroll PIC_EVAL_UNROLL
         for (int c = 0; c < 3; ++c) {
             T r0 = 0, r1 = 0, r2 = 0;
 #pragma unroll
@@ -228,6 +230,108 @@ __device__ __forceinline__ void eval_q2_refgrad(const MeshDev &m, const typename
                     if constexpr (D == 3) G[c][2] += vc[c] * w2;
                 }
             }
+}
+
+// ---------------------------------------------------------------------------
+// uniform meshes: (i,j,k) carried through location and evaluation
+// ---------------------------------------------------------------------------
+// global-address-space pointer (global_load instead of flat_load); the host
+// pass of the compiler sees a plain pointer
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename V> using gptr = const V __attribute__((address_space(1))) *;
+#else
+template <typename V> using gptr = const V *;
+#endif
+
+// (i,j,k) of cell K with 32-bit arithmetic (cells < 2^31)
+template <int D>
+__device__ __forceinline__ void ijk_of(const MeshDev &m, uint32_t K, int ijk[3])
+{
+    const uint32_t n0 = (uint32_t)m.n[0];
+    const uint32_t q = K / n0;
+    ijk[0] = (int)(K - q * n0);
+    if constexpr (D == 3) {
+        const uint32_t n1 = (uint32_t)m.n[1];
+        const uint32_t r = q / n1;
+        ijk[1] = (int)(q - r * n1);
+        ijk[2] = (int)r;
+    } else {
+        ijk[1] = (int)q;
+        ijk[2] = 0;
+    }
+}
+
+template <int D> __device__ __forceinline__ uint32_t cell_of(const MeshDev &m, const int ijk[3])
+{
+    uint32_t K = (uint32_t)ijk[0] + (uint32_t)m.n[0] * (uint32_t)ijk[1];
+    if constexpr (D == 3) K += (uint32_t)m.n[0] * (uint32_t)m.n[1] * (uint32_t)ijk[2];
+    return K;
+}
+
+// Owning cell of y by the closed form floor((y - lo)/h) with the half-open
+// rule (upper domain faces closed); false outside the closed box.
+template <int D>
+__device__ __forceinline__ bool locate_uniform(const MeshDev &m, const double *y, int ijk[3], double *t)
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        inside &= (y[a] >= m.lo[a]) & (y[a] <= m.hi[a]);
+        const double s = (y[a] - m.lo[a]) * m.inv_h[a];
+        int i = (int)floor(s);
+        i = i >= m.n[a] ? m.n[a] - 1 : (i < 0 ? 0 : i);
+        t[a] = (y[a] - fma((double)i, m.h[a], m.lo[a])) * m.inv_h[a];
+        ijk[a] = i;
+    }
+    if constexpr (D == 2) ijk[2] = 0;
+    return inside;
+}
+
+// Q2 evaluation on a structured node grid from (i,j,k), sum-factorised.
+template <int D, typename T>
+__device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U, int nnx, int nny, const int ijk[3],
+                                            const double *tr, double *u)
+{
+    T la[3], lb[3];
+    lag3((T)tr[0], la);
+    lag3((T)tr[1], lb);
+    if constexpr (D == 2) {
+        const int base = 2 * ijk[0] + nnx * (2 * ijk[1]);
+        T a0 = 0, a1 = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int r = base + nnx * b;
+            const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
+            a0 += lb[b] * (la[0] * v0.x + la[1] * v1.x + la[2] * v2.x);
+            a1 += lb[b] * (la[0] * v0.y + la[1] * v1.y + la[2] * v2.y);
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+    } else {
+        T lc[3];
+        lag3((T)tr[2], lc);
+        const int sz = nnx * nny;
+        const int base = 2 * ijk[0] + nnx * (2 * ijk[1]) + sz * (2 * ijk[2]);
+        T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int r = base + nnx * b + sz * c;
+                const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
+                r0 += lb[b] * (la[0] * v0.x + la[1] * v1.x + la[2] * v2.x);
+                r1 += lb[b] * (la[0] * v0.y + la[1] * v1.y + la[2] * v2.y);
+                r2 += lb[b] * (la[0] * v0.z + la[1] * v1.z + la[2] * v2.z);
+            }
+            a0 += lc[c] * r0;
+            a1 += lc[c] * r1;
+            a2 += lc[c] * r2;
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+        u[2] = (double)a2;
+    }
 }
 
 // ---------------------------------------------------------------------------

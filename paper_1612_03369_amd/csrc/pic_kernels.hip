@@ -70,6 +70,70 @@ __device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename 
     return (uint32_t)Kn;
 }
 
+// Uniform meshes: the same step with (i,j,k) carried along (no index division
+// after the first) and the closed-form location.
+template <int D, int S, typename T>
+__device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<typename NodeVec<D, T>::type> U, double dt,
+                                                       double *x, double *t, uint32_t K, bool &near)
+{
+    int ijk[3], jk[3];
+    double u[3], k1[3], y[3], ty[3], xn[3];
+    ijk_of<D>(m, K, ijk);
+    eval_q2_ijk<D, T>(U, m.nnx, m.nny, ijk, t, u);
+#pragma unroll
+    for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
+    bool in = true;
+    if constexpr (S == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a];
+    } else if constexpr (S == 2) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
+    } else {
+        double k2[3], k3[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k2[a] = dt * u[a];
+            y[a] = x[a] + 0.5 * k2[a];
+        }
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k3[a] = dt * u[a];
+            y[a] = x[a] + k3[a];
+        }
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
+        const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
+    }
+    near |= near_boundary<D>(m, xn);
+    double tn[3];
+    in &= locate_uniform<D>(m, xn, jk, tn);
+    if (!in) return LOST;
+    near |= face_dist<D>(tn) < NEAR_TOL;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = xn[a];
+        t[a] = tn[a];
+    }
+    return cell_of<D>(m, jk);
+}
+
 // Accumulate per-thread counters into the device statistics (one atomic per
 // counter per workgroup).
 __device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot, int v, int *s_red)
@@ -79,84 +143,72 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot,
 }
 
 /*
- * Work item = tile of consecutive cells [c0, c1) of one problem.  The tile's
- * particles are contiguous in the store; they are processed in chunks of
- * BLOCK.  For every particle: advance + locate, write the new location and
- * reference location in place, its key (new cell or LOST), and for particles
- * that stay in their cell their rank among the cell's stayers (prefix scan of
- * stay flags; the rank of a cell's first particle is the base).  Per-cell
- * stayer counts stay in LDS; arrivals are counted with global atomics.
+ * Work item = tile of consecutive cells [c0, c1) of one problem; its
+ * particles are contiguous in the store.  For every particle: advance +
+ * locate, write the new location and reference location in place and the
+ * key (new cell or LOST).  Stayers are counted per cell in LDS, arrivals with
+ * global atomics on the destination cell.
  */
+#ifndef PIC_ADVECT_MIN_WAVES
+#define PIC_ADVECT_MIN_WAVES 0      // 0: compiler's choice; N: cap registers for N waves per SIMD
+#endif
+#if PIC_ADVECT_MIN_WAVES > 0
+#define PIC_ADVECT_ATTR __attribute__((amdgpu_waves_per_eu(PIC_ADVECT_MIN_WAVES)))
+#else
+#define PIC_ADVECT_ATTR
+#endif
 template <int D, int S, typename T, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_advect(const ProblemDev *__restrict__ probs, const WorkItem *__restrict__ work,
-                                                  int n_work)
+__global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemDev *__restrict__ probs,
+                                                                  const WorkItem *__restrict__ work, int n_work)
 {
-    __shared__ int s_cs[MAX_TILE + 1];
-    __shared__ int s_base[MAX_TILE];
     __shared__ int s_cnt[MAX_TILE];
-    __shared__ int s_wave[BLOCK / 64];
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
         const WorkItem wi = work[w];
         const ProblemDev &P = probs[wi.problem];
         const MeshDev &m = P.mesh;
-        const auto *U = reinterpret_cast<const typename NodeVec<D, T>::type *>(
-            sizeof(T) == 4 ? P.u32 : P.u64);
         const StoreDev cur = P.store[P.cur];
         const int64_t cap = P.cap;
         const double dt = P.dt;
         const int c0 = wi.c0, nt = wi.c1 - wi.c0;
-        for (int k = threadIdx.x; k <= nt; k += BLOCK) s_cs[k] = cur.cs[c0 + k];
+        const int p0 = cur.cs[c0], p1 = cur.cs[wi.c1];
         for (int k = threadIdx.x; k < nt; k += BLOCK) s_cnt[k] = 0;
         __syncthreads();
-        const int p0 = s_cs[0], p1 = s_cs[nt];
-        int carry = 0;
         int st_lost = 0, st_moved = 0, st_near = 0;
         LocStats ls = {0, 0, 0, 0};
-        for (int base = p0; base < p1; base += BLOCK) {
-            const int i = base + threadIdx.x;
-            const bool active = i < p1;
-            int stay = 0, kloc = 0;
-            uint32_t key = LOST;
-            if (active) {
-                const int32_t K = cur.cell[i];
-                kloc = K - c0;
-                double x[3], t[3];
+        for (int i = p0 + threadIdx.x; i < p1; i += BLOCK) {
+            const int32_t K = cur.cell[i];
+            double x[3], t[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                x[a] = cur.x[a * cap + i];
+                t[a] = cur.xr[a * cap + i];
+            }
+            bool near = false;
+            uint32_t key;
+            if constexpr (KIND == MESH_UNIFORM) {
+                using V = typename NodeVec<D, T>::type;
+                auto U = (gptr<V>)(sizeof(T) == 4 ? P.u32 : P.u64);
+                key = advect_one_uniform<D, S, T>(m, U, dt, x, t, (uint32_t)K, near);
+            } else {
+                const auto *U = reinterpret_cast<const typename NodeVec<D, T>::type *>(sizeof(T) == 4 ? P.u32 : P.u64);
+                key = advect_one<D, S, T, KIND>(m, U, dt, x, t, K, near, ls);
+            }
+            if (key != LOST) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    x[a] = cur.x[a * cap + i];
-                    t[a] = cur.xr[a * cap + i];
-                }
-                bool near = false;
-                key = advect_one<D, S, T, KIND>(m, U, dt, x, t, K, near, ls);
-                if (key != LOST) {
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        cur.x[a * cap + i] = x[a];
-                        cur.xr[a * cap + i] = t[a];
-                    }
-                }
-                stay = key == (uint32_t)K;
-                st_lost += key == LOST;
-                st_moved += (key != LOST) && !stay;
-                st_near += near;
-                P.scr.key[i] = key;
-            }
-            int total;
-            const int pre = block_scan_flags(stay, s_wave, total);
-            const int Pi = carry + pre;
-            if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
-            __syncthreads();
-            if (active) {
-                if (stay) {
-                    P.scr.slot[i] = (uint32_t)(Pi - s_base[kloc]);
-                    atomicAdd(&s_cnt[kloc], 1);
-                } else if (key != LOST) {
-                    atomicAdd(&P.scr.n_arrive[key], 1);
+                    cur.x[a * cap + i] = x[a];
+                    cur.xr[a * cap + i] = t[a];
                 }
             }
-            carry += total;
-            __syncthreads();
+            P.scr.key[i] = key;
+            const bool stay = key == (uint32_t)K;
+            if (stay) atomicAdd(&s_cnt[K - c0], 1);
+            else if (key != LOST) atomicAdd(&P.scr.n_arrive[key], 1);
+            st_lost += key == LOST;
+            st_moved += (key != LOST) && !stay;
+            st_near += near;
         }
+        __syncthreads();
         for (int k = threadIdx.x; k < nt; k += BLOCK) P.scr.n_stay[c0 + k] = s_cnt[k];
         flush_stats(P.scr.stats, ST_PSTEPS, threadIdx.x == 0 ? p1 - p0 : 0, nullptr);
         flush_stats(P.scr.stats, ST_LOST, st_lost, nullptr);
@@ -298,10 +350,65 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
 // ===========================================================================
 // place / fix / gather: the stable re-sort by (new cell, moved)
 // ===========================================================================
-// Destination of every particle of the current buffer.  Stayers go to
-// new_start[K] + rank; arrivals get a provisional slot after the stayers.
-__global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
-                                                 int n_items)
+/*
+ * Destination of every particle of a tile of cells.  Stayers go to
+ * new_start[K] + (rank among the cell's stayers): a workgroup prefix scan of
+ * stay flags in store order, minus the scan value at the cell's first
+ * particle.  Arrivals get a provisional slot after the destination cell's
+ * stayers from an atomic cursor; k_fix orders them afterwards.
+ */
+__global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ probs, const WorkItem *__restrict__ work,
+                                                 int n_work)
+{
+    __shared__ int s_cs[MAX_TILE + 1];
+    __shared__ int s_base[MAX_TILE];
+    __shared__ int s_wave[BLOCK / 64];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const WorkItem wi = work[w];
+        const ProblemDev &P = probs[wi.problem];
+        const StoreDev cur = P.store[P.cur];
+        const StoreDev nxt = P.store[1 - P.cur];
+        const int c0 = wi.c0, nt = wi.c1 - wi.c0;
+        for (int k = threadIdx.x; k <= nt; k += BLOCK) s_cs[k] = cur.cs[c0 + k];
+        __syncthreads();
+        const int p0 = s_cs[0], p1 = s_cs[nt];
+        int carry = 0;
+        for (int base = p0; base < p1; base += BLOCK) {
+            const int i = base + threadIdx.x;
+            const bool active = i < p1;
+            uint32_t key = LOST;
+            int K = c0;
+            if (active) {
+                key = P.scr.key[i];
+                K = cur.cell[i];
+            }
+            const int stay = active && key == (uint32_t)K;
+            int total;
+            const int pre = block_scan_flags(stay, s_wave, total);
+            const int Pi = carry + pre;
+            const int kloc = K - c0;
+            if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
+            __syncthreads();
+            if (active && key != LOST) {
+                int64_t dst;
+                if (stay) {
+                    dst = (int64_t)nxt.cs[K] + (Pi - s_base[kloc]);
+                } else {
+                    const int r = atomicAdd(&P.scr.cursor[key], 1);
+                    dst = (int64_t)nxt.cs[key] + P.scr.n_stay[key] + r;
+                }
+                P.scr.src[dst] = i;
+            }
+            carry += total;
+            __syncthreads();
+        }
+    }
+}
+
+// Placement of an unsorted input (prescribed locations): every particle is an
+// arrival in its cell.
+__global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__restrict__ probs,
+                                                          const RangeItem *__restrict__ items, int n_items)
 {
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const RangeItem it = items[w];
@@ -313,14 +420,8 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
         if (i >= n || i >= it.end) continue;
         const uint32_t key = P.scr.key[i];
         if (key == LOST) continue;
-        int64_t dst;
-        if (key == (uint32_t)cur.cell[i]) {
-            dst = (int64_t)nxt.cs[key] + P.scr.slot[i];
-        } else {
-            int r = atomicAdd(&P.scr.cursor[key], 1);
-            dst = (int64_t)nxt.cs[key] + P.scr.n_stay[key] + r;
-        }
-        P.scr.src[dst] = (int32_t)i;
+        const int r = atomicAdd(&P.scr.cursor[key], 1);
+        P.scr.src[(int64_t)nxt.cs[key] + P.scr.n_stay[key] + r] = (int32_t)i;
     }
 }
 
@@ -413,7 +514,8 @@ __global__ void k_flip(ProblemDev *probs, int n_probs, int count_step)
 // ===========================================================================
 // generation (Sec. 2.2)
 // ===========================================================================
-// Reference-local generation: particle p of cell K at x = Phi_K(xr).
+// Reference-local generation: one wavefront per cell K writes the cell's
+// particles p in [cs[K], cs[K+1]) at x = Phi_K(xr).
 template <int D, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int prob, const double *__restrict__ xr_in,
                                                           const uint32_t *__restrict__ ids, int64_t n, int prop_init,
@@ -423,31 +525,30 @@ __global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int
     const MeshDev &m = P.mesh;
     const StoreDev cur = P.store[P.cur];
     const int64_t cap = P.cap;
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= n) return;
-    // owning cell: last K with cs[K] <= p
-    int64_t lo = 0, hi = m.n_cells;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) / 2;
-        if (cur.cs[mid] <= p) lo = mid; else hi = mid;
+    const int64_t K = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (K >= m.n_cells) return;
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1];
+    unsigned long long idmax = 0;
+    for (int64_t p = b + lane; p < e && p < n; p += 64) {
+        double t[3], x[3];
+        for (int a = 0; a < D; ++a) t[a] = xr_in[a * n + p];
+        map_to_real<D, KIND>(m, K, t, x);
+        for (int a = 0; a < D; ++a) {
+            cur.x[a * cap + p] = x[a];
+            cur.xr[a * cap + p] = t[a];
+        }
+        cur.cell[p] = (int32_t)K;
+        cur.id[p] = ids[p];
+        for (int j = 0; j < P.n_prop; ++j) {
+            double v = prop_init == 1 ? x[j % D]
+                                      : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
+            if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
+            else ((float *)cur.prop)[j * cap + p] = (float)v;
+        }
+        idmax = idmax > (unsigned long long)ids[p] + 1ull ? idmax : (unsigned long long)ids[p] + 1ull;
     }
-    const int64_t K = lo;
-    double t[3], x[3];
-    for (int a = 0; a < D; ++a) t[a] = xr_in[a * n + p];
-    map_to_real<D, KIND>(m, K, t, x);
-    for (int a = 0; a < D; ++a) {
-        cur.x[a * cap + p] = x[a];
-        cur.xr[a * cap + p] = t[a];
-    }
-    cur.cell[p] = (int32_t)K;
-    cur.id[p] = ids[p];
-    for (int j = 0; j < P.n_prop; ++j) {
-        double v = prop_init == 1 ? x[j % D]
-                                  : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
-        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
-        else ((float *)cur.prop)[j * cap + p] = (float)v;
-    }
-    atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);
+    if (idmax) atomicMax(P.scr.next_id, idmax);
 }
 
 // Prescribed locations: locate each point with the global search and write it

@@ -270,6 +270,52 @@ def octree_shell_leaves(base_level=3, max_level=7, r_in=0.35, r_out=0.45, width=
     return L[order].astype(np.uint8), np.ascontiguousarray(A[:, order].astype(np.int32))
 
 
+def balance_octree(level, anchor, max_level):
+    """Refine leaves until every pair of leaves sharing at least a point differs by
+    at most one level (vertex 2:1 balance).  Returns leaves in Morton order.
+    Plain loops: meant for small meshes."""
+    fine = 1 << max_level
+    lv = [int(v) for v in level]
+    an = [tuple(int(anchor[a][k]) for a in range(3)) for k in range(len(lv))]
+    while True:
+        table = np.empty((fine, fine, fine), np.int64)
+        for k, (l, a) in enumerate(zip(lv, an)):
+            s = 1 << (max_level - l)
+            table[a[2]:a[2] + s, a[1]:a[1] + s, a[0]:a[0] + s] = k
+        levels = np.array(lv)
+        refine = []
+        for k, (l, a) in enumerate(zip(lv, an)):
+            s = 1 << (max_level - l)
+            lo = [max(v - 1, 0) for v in a]
+            hi = [min(v + s + 1, fine) for v in a]
+            nb = np.unique(table[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+            if levels[nb].max() > l + 1:
+                refine.append(k)
+        if not refine:
+            break
+        rset = set(refine)
+        nl, na = [], []
+        for k, (l, a) in enumerate(zip(lv, an)):
+            if k not in rset:
+                nl.append(l)
+                na.append(a)
+                continue
+            h = 1 << (max_level - l - 1)
+            for dz in (0, 1):
+                for dy in (0, 1):
+                    for dx in (0, 1):
+                        nl.append(l + 1)
+                        na.append((a[0] + dx * h, a[1] + dy * h, a[2] + dz * h))
+        lv, an = nl, na
+    A = np.array(an, np.int64).T
+    key = np.zeros(A.shape[1], dtype=np.uint64)
+    for bit in range(max_level):
+        for ax in range(3):
+            key |= ((A[ax].astype(np.uint64) >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + ax)
+    order = np.argsort(key, kind="stable")
+    return np.array(lv, np.uint8)[order], np.ascontiguousarray(A[:, order].astype(np.int32))
+
+
 # --------------------------------------------------------------------------
 # workload configurations
 # --------------------------------------------------------------------------

@@ -1,0 +1,323 @@
+"""GPU parity of the remaining hot-path rows: population management, least
+squares, batched problems, the adjoint, displaced meshes, octree meshes and
+prescribed-location seeding."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1612_03369_amd import inputs as I
+
+from helpers import compare_stores, gpu_problem, oracle_run_tracking, oracle_store
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1612_03369_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _fourier_cfg(dim, n, counts_hi, seed, n_prop=1, prop_dtype=np.float64, tangential=False):
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    f = I.FourierField(dim, seed=seed, tangential=tangential)
+    U = I.normalise_nodal(I.sample_nodes(f.velocity, I.uniform_q2_nodes(mesh)))
+    rng = np.random.default_rng(seed + 1)
+    counts = rng.integers(0, counts_hi, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=seed + 2)
+    return dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=n_prop, prop_dtype=prop_dtype)
+
+
+# ----------------------------------------------------------------------------
+def test_population_matches_oracle(L):
+    """Advance + population each step (min 4 / max 9): ids, locations, properties."""
+    _say("case: population 3D 8^3, counts 0..14, clamp [4, 9], 4 steps")
+    cfg = _fourier_cfg(3, 8, 15, seed=101, n_prop=2)
+    cap = 10 * cfg["mesh"].n_cells + 100
+    p = gpu_problem(cfg, capacity=cap)
+    om, st = oracle_store(cfg, cap=cap)
+    nid = int(cfg["ids"].max()) + 1
+    dt = 0.5 / 8
+    near = set()
+    for step in range(4):
+        p.advance(dt, 1, L.PIC_RK2, L.PIC_F64)
+        p.population(4, 9, 40, step)
+        nr, _ = oracle_run_tracking(om, cfg["U"], dt, 2, 1, st)
+        near |= nr
+        nid, added, deleted = O.population(om, st, 4, 9, 40, step, nid)
+    g = p.numpy()
+    o = st.view()
+    s = p.stats()
+    cnt = np.diff(g["cell_start"])
+    assert cnt.min() >= 4 and cnt.max() <= 9
+    assert np.unique(g["id"]).size == g["n"]
+    compare_stores(g, o, near, pos_tol=1e-12)
+    if not near:
+        assert np.array_equal(g["id"], o["id"])
+        assert np.abs(g["prop"] - o["prop"]).max() < 1e-13
+        assert np.abs(g["xr"] - o["xr"]).max() < 1e-14
+    _say(f"  live {g['n']}, added {s['added']}, deleted {s['deleted']}, near {len(near)}")
+    assert s["added"] > 0 and s["deleted"] > 0
+    p.close()
+
+
+def test_population_capacity_error(L):
+    cfg = _fourier_cfg(2, 6, 3, seed=111)
+    p = gpu_problem(cfg, capacity=cfg["xr"].shape[1] + 5)
+    from paper_1612_03369_amd._lib import PicError
+    with pytest.raises(PicError) as e:
+        p.population(20, 30, 1, 0)
+    assert e.value.status == L.PIC_ECAPACITY
+    p.close()
+
+
+def test_linear_least_squares_matches_oracle(L):
+    _say("case: least squares 3D 6^3 after 3 RK2 steps")
+    cfg = _fourier_cfg(3, 6, 12, seed=121, n_prop=2)
+    p = gpu_problem(cfg)
+    p.advance(0.5 / 6, 3, L.PIC_RK2, L.PIC_F64)
+    out, xbar, cnt = p.interpolate(L.PIC_INTERP_LINEAR_LS)
+    g = p.numpy()
+    coef_o, xbar_o = O.linear_least_squares(cfg["mesh"].n_cells, 3, g["cell_start"], g["xr"], g["prop"])
+    c = cnt.cpu().numpy()
+    assert np.array_equal(c, np.diff(g["cell_start"]))
+    og, xg = out.cpu().numpy(), xbar.cpu().numpy()
+    ok = c > 0
+    assert np.all(np.isnan(og[~ok]))
+    assert np.allclose(xg[ok], xbar_o[ok], rtol=0, atol=1e-14)
+    assert np.allclose(og[ok], coef_o[ok], rtol=1e-9, atol=1e-11)
+    p.close()
+
+
+def test_linear_least_squares_reproduces_linear_data(L):
+    """Initial-position property is linear in the reference coordinates: exact recovery."""
+    cfg = _fourier_cfg(2, 10, 9, seed=131, n_prop=2)
+    p = gpu_problem(cfg)
+    out, xbar, cnt = p.interpolate(L.PIC_INTERP_LINEAR_LS)
+    c = cnt.cpu().numpy()
+    o = out.cpu().numpy()
+    h = 0.1
+    full = c >= 3
+    # property j = x_j = (i_j + xr_j) h: slope h along axis j, zero along the other
+    assert np.allclose(o[full, 0, 1], h, atol=1e-12) and np.allclose(o[full, 0, 2], 0, atol=1e-12)
+    assert np.allclose(o[full, 1, 2], h, atol=1e-12) and np.allclose(o[full, 1, 1], 0, atol=1e-12)
+    p.close()
+
+
+# ----------------------------------------------------------------------------
+def test_batch_bit_identical_to_single_runs(L):
+    _say("case: batch of 6 mixed problems vs single runs")
+    from paper_1612_03369_amd.api import Batch
+    cfgs = []
+    for q in range(6):
+        dim = 2 + (q % 2)
+        n = 20 if dim == 2 else 8
+        c = _fourier_cfg(dim, n, 10, seed=200 + q)
+        c["scheme"] = (2, 4)[(q // 2) % 2] if q != 5 else 1
+        c["dt"] = 0.5 / n
+        cfgs.append(c)
+    singles = []
+    for c in cfgs:
+        p = gpu_problem(c)
+        p.advance(c["dt"], 7, c["scheme"], L.PIC_F64)
+        singles.append(p.numpy())
+        p.close()
+    probs = [gpu_problem(c) for c in cfgs]
+    b = Batch(probs, tile_cells=(16, 32, 8, 16))
+    b.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 4)
+    b.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 3)
+    for p, s in zip(probs, singles):
+        g = p.numpy()
+        for k in ("x", "xr", "cell", "id", "prop", "cell_start"):
+            assert np.array_equal(g[k], s[k]), k
+        assert p.stats()["steps"] == 7
+    b.close()
+    for p in probs:
+        p.close()
+
+
+# ----------------------------------------------------------------------------
+def _adjoint_case(L, n=6, ppc=3, steps=8, scheme=4, ckpt=3, seed=301):
+    mesh = I.UniformMesh(3, (n, n, n))
+    nodes = I.uniform_q2_nodes(mesh)
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=seed, tangential=True).velocity, nodes))
+    counts = np.full(mesh.n_cells, ppc, np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=seed + 1)
+    cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=0, prop_dtype=np.float64)
+    return cfg, 0.5 / n, steps, scheme, ckpt
+
+
+@pytest.mark.parametrize("scheme", [2, 4])
+def test_adjoint_matches_oracle_gradient(L, scheme):
+    _say(f"case: adjoint vs oracle, scheme {scheme}")
+    import torch
+    from paper_1612_03369_amd.adjoint import ParticleFlow, advect
+    cfg, dt, steps, _, ckpt = _adjoint_case(L, scheme=scheme)
+    p = gpu_problem(cfg)
+    flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, scheme, ckpt)
+    U = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device, requires_grad=True)
+    xT = advect(U, flow)
+    rng = np.random.default_rng(7)
+    tgt = torch.tensor(xT.detach().cpu().numpy() + 0.01 * rng.standard_normal(xT.shape), device=p.device)
+    mask = ~torch.isnan(xT[0])
+    nv = int(mask.sum())
+    loss = ((xT - tgt)[:, mask] ** 2).sum() / nv
+    loss.backward()
+    g = U.grad.cpu().numpy()
+    # oracle: per-particle reverse sweep from the initial state
+    om, st = oracle_store(cfg)
+    v = st.view()
+    tg = tgt.cpu().numpy()[:, v["id"]]
+    m = mask.cpu().numpy()[v["id"]].astype(np.uint8)
+    Lo, dUo, lost = O.adjoint(om, cfg["U"], dt, scheme, steps, v["x"], v["cell"], v["xr"], tg, m)
+    assert abs(float(loss) - Lo) <= 1e-12 * abs(Lo)
+    assert np.abs(g - dUo).max() <= 1e-10 * np.abs(dUo).max(), np.abs(g - dUo).max() / np.abs(dUo).max()
+    p.close()
+
+
+def test_adjoint_central_differences(L):
+    _say("case: adjoint vs central differences (GPU forward)")
+    import torch
+    from paper_1612_03369_amd.adjoint import ParticleFlow, advect
+    cfg, dt, steps, scheme, ckpt = _adjoint_case(L, n=5, ppc=4, steps=10, ckpt=4, seed=311)
+    p = gpu_problem(cfg)
+    flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, scheme, ckpt)
+    U0 = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device)
+    with torch.no_grad():
+        x0, _ = flow.run_forward(U0, checkpoint=False)
+    tgt = x0 + 0.02
+    mask = ~torch.isnan(x0[0])
+
+    def loss_of(U):
+        xT = advect(U, flow)
+        return ((xT - tgt)[:, mask] ** 2).sum() / int(mask.sum())
+
+    U = U0.clone().requires_grad_(True)
+    loss_of(U).backward()
+    g = U.grad.clone()
+    rng = np.random.default_rng(8)
+    for _ in range(6):
+        d = torch.tensor(rng.standard_normal(cfg["U"].shape), device=p.device)
+        d /= d.abs().max()
+        eps = 1e-6
+        with torch.no_grad():
+            lp = float(loss_of(U0 + eps * d))
+            lm = float(loss_of(U0 - eps * d))
+        fd = (lp - lm) / (2 * eps)
+        an = float((g * d).sum())
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-12), (fd, an)
+    p.close()
+
+
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_displaced_mesh_newton_and_neighbour_search(L, dim):
+    _say(f"case: displaced mesh dim {dim}")
+    from paper_1612_03369_amd.api import Problem
+    n = (6, 5) if dim == 2 else (4, 4, 3)
+    mesh = I.UniformMesh(dim, n)
+    vert = I.displaced_vertices(mesh, 0.2, seed=400 + dim)
+    om = O.OracleMesh.displaced(mesh, vert)
+    nodes = om.q2_node_coords()
+    f = I.FourierField(dim, seed=410 + dim)
+    U = I.normalise_nodal(I.sample_nodes(f.velocity, nodes))
+    rng = np.random.default_rng(420 + dim)
+    counts = rng.integers(0, 8, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=430 + dim)
+    p = Problem(0)
+    p.mesh_uniform(dim, n)
+    p.mesh_displace(vert)
+    gx, _ = p.q2_nodes()
+    assert np.allclose(gx, nodes, atol=1e-15)
+    p.set_velocity(U)
+    p.allocate(xr.shape[1], n_prop=1)
+    p.seed_reference(counts, xr, ids)
+    dt = 0.3 / max(n)
+    p.advance(dt, 6, L.PIC_RK4, L.PIC_F64)
+    g = p.numpy()
+    st = O.seed(om, counts, xr, ids, 1)
+    near, _ = oracle_run_tracking(om, U, dt, 4, 6, st)
+    err, nn = compare_stores(g, st.view(), near, pos_tol=1e-12)
+    s = p.stats()
+    _say(f"  moved {s['moved']}, first-try {s['first_try']}, fallback {s['fallback']}, newton_fail {s['newton_fail']}")
+    assert s["first_try"] > 0
+    p.close()
+
+
+# ----------------------------------------------------------------------------
+def _small_octree():
+    """Base 2^3 refined toward a corner region (levels 1..4), 2:1 balanced."""
+    level, anchor = I.octree_shell_leaves(base_level=1, max_level=4, r_in=0.0, r_out=0.3, width=1.0,
+                                          centre=(0.3, 0.35, 0.4))
+    return I.balance_octree(level, anchor, 4)
+
+
+def test_octree_mesh_parity(L):
+    _say("case: small octree, RK2")
+    from paper_1612_03369_amd.api import Problem
+    level, anchor = _small_octree()
+    om = O.OracleMesh.octree(level, anchor, 4)
+    nodes = om.q2_node_coords()
+    f = I.FourierField(3, seed=501)
+    U = om.resolve_hanging(I.normalise_nodal(I.sample_nodes(f.velocity, nodes)))
+    counts = np.random.default_rng(502).integers(0, 9, level.size).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=503)
+    p = Problem(0)
+    p.mesh_octree(level, anchor, 4)
+    gx, ghang = p.q2_nodes()
+    assert np.array_equal(gx, nodes)
+    hang = np.zeros(nodes.shape[1], bool)
+    hang[[nd for nd, _ in om.hanging_constraints()]] = True
+    assert np.array_equal(ghang, hang)
+    Uraw = I.normalise_nodal(I.sample_nodes(f.velocity, nodes))
+    p.set_velocity(Uraw)                     # the library resolves hanging nodes itself
+    p.allocate(xr.shape[1], n_prop=1)
+    p.seed_reference(counts, xr, ids)
+    dt = 0.5 / 16
+    p.advance(dt, 8, L.PIC_RK2, L.PIC_F64)
+    g = p.numpy()
+    st = O.seed(om, counts, xr, ids, 1)
+    near, _ = oracle_run_tracking(om, U, dt, 2, 8, st)
+    compare_stores(g, st.view(), near, pos_tol=1e-12)
+    s = p.stats()
+    _say(f"  moved {s['moved']}, first-try {s['first_try']}, fallback {s['fallback']}")
+    p.close()
+
+
+def test_seed_positions_matches_oracle_locate(L):
+    _say("case: prescribed locations")
+    from paper_1612_03369_amd.api import Problem
+    mesh = I.UniformMesh(3, (5, 4, 3))
+    rng = np.random.default_rng(600)
+    x = rng.uniform(-0.1, 1.1, size=(3, 3000))
+    x[:, :50] = np.round(x[:, :50] * 4) / 4            # points on faces
+    ids = np.arange(3000, dtype=np.uint32)
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(np.zeros((3, mesh.n_nodes)))
+    p.allocate(3000, n_prop=1)
+    p.seed_positions(x, ids)
+    g = p.numpy()
+    om = O.OracleMesh.uniform(mesh)
+    exp = []
+    for i in range(3000):
+        K, t = om.locate(x[:, i])
+        if K is not None:
+            exp.append((K, i))
+    exp.sort()
+    assert g["id"].tolist() == [i for _, i in exp]
+    assert g["cell"].tolist() == [K for K, _ in exp]
+    assert np.array_equal(g["x"], x[:, g["id"]])
+    assert p.stats()["lost"] == 3000 - len(exp)
+    p.close()
