@@ -61,6 +61,8 @@ struct pic_ctx {
     int n_rp = 0;
     RangeItem *d_rc = nullptr;   // cell ranges
     int n_rc = 0;
+    BlockItem *d_blk[2] = {nullptr, nullptr};   // uniform meshes: cell blocks for F64 / F32 evaluation
+    int n_blk[2] = {0, 0};
     double last_dt = std::nan("");
     // profiling
     bool profile = false;
@@ -242,6 +244,29 @@ pic_status upload_problem(pic_ctx *c)
     return PIC_OK;
 }
 
+#ifndef PIC_USE_BLOCK_ADVECT
+#define PIC_USE_BLOCK_ADVECT 1
+#endif
+// Cell-block shapes of the LDS-staged advect (uniform meshes) per (dim, precision).
+constexpr int BLK3_F32[3] = {4, 4, 4};
+constexpr int BLK3_F64[3] = {4, 4, 2};
+constexpr int BLK2[3] = {8, 8, 1};
+inline const int *block_shape(int dim, int prec)
+{
+    return dim == 2 ? BLK2 : (prec == PIC_F32 ? BLK3_F32 : BLK3_F64);
+}
+
+std::vector<BlockItem> block_items(const MeshDev &m, int prec, int problem)
+{
+    const int *b = block_shape(m.dim, prec);
+    std::vector<BlockItem> v;
+    const int nz = m.dim == 3 ? m.n[2] : 1, bz = m.dim == 3 ? b[2] : 1;
+    for (int k = 0; k < nz; k += bz)
+        for (int j = 0; j < m.n[1]; j += b[1])
+            for (int i = 0; i < m.n[0]; i += b[0]) v.push_back({problem, i, j, k});
+    return v;
+}
+
 // Work lists for one problem.
 pic_status build_work(pic_ctx *c)
 {
@@ -269,6 +294,16 @@ pic_status build_work(pic_ctx *c)
     HIPCHK(c, hipMemcpy(c->d_scan, sc.data(), sc.size() * sizeof(ScanItem), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_rp, rp.data(), rp.size() * sizeof(RangeItem), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_rc, rc.data(), rc.size() * sizeof(RangeItem), hipMemcpyHostToDevice));
+    for (int pr = 0; pr < 2; ++pr) {
+        if (c->d_blk[pr]) hipFree(c->d_blk[pr]);
+        c->d_blk[pr] = nullptr;
+        c->n_blk[pr] = 0;
+        if (c->mesh.kind != MESH_UNIFORM) continue;
+        std::vector<BlockItem> bl = block_items(c->mesh, pr, 0);
+        if ((s = dalloc(c, &c->d_blk[pr], bl.size()))) return s;
+        HIPCHK(c, hipMemcpy(c->d_blk[pr], bl.data(), bl.size() * sizeof(BlockItem), hipMemcpyHostToDevice));
+        c->n_blk[pr] = (int)bl.size();
+    }
     c->n_work = (int)w.size();
     c->n_scan = (int)sc.size();
     c->n_rp = (int)rp.size();
@@ -353,8 +388,36 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
     return PIC_OK;
 }
 
+using BlockFn = void (*)(const ProblemDev *, const BlockItem *, int);
+template <int D, int S> BlockFn block_for_prec(int prec)
+{
+    if constexpr (D == 3) {
+        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2]>;
+        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2]>;
+    } else {
+        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1>;
+        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1>;
+    }
+}
+template <int D> BlockFn block_for_scheme(int scheme, int prec)
+{
+    switch (scheme) {
+    case PIC_EULER: return block_for_prec<D, 1>(prec);
+    case PIC_RK2: return block_for_prec<D, 2>(prec);
+    case PIC_RK4: return block_for_prec<D, 4>(prec);
+    }
+    return nullptr;
+}
+
 pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
 {
+    if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
+        BlockFn f = c->mesh.dim == 2 ? block_for_scheme<2>(scheme, prec) : block_for_scheme<3>(scheme, prec);
+        const int pr = prec == PIC_F32;
+        LAUNCH(c, "advect", f, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
+               c->n_blk[pr]);
+        return enqueue_sort(c, dp, 1);
+    }
     AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind);
     if (!f) return fail(c, PIC_EINVAL, "unsupported combination dim=%d scheme=%d kind=%d", c->mesh.dim, scheme, c->mesh.kind);
     LAUNCH(c, "advect", f, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
@@ -395,7 +458,7 @@ extern "C" void pic_destroy(pic_ctx *c)
     else hipDeviceSynchronize();
     free_mesh(c);
     for (void *p : {c->u64, c->u32, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
-                    (void *)c->d_rc})
+                    (void *)c->d_rc, (void *)c->d_blk[0], (void *)c->d_blk[1]})
         if (p) hipFree(p);
     for (auto &p : c->pending) {
         hipEventDestroy(p.a);

@@ -89,13 +89,29 @@ __device__ __forceinline__ float nv_z(const float2 &) { return 0.f; }
 __device__ __forceinline__ double nv_z(const double2 &) { return 0.0; }
 
 // ---------------------------------------------------------------------------
+// rounding-pinned building blocks of the sum-factorised evaluation: every
+// evaluation path (global memory, LDS window, octree node map) combines node
+// values with exactly these fused multiply-adds, so they agree bit for bit
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// s = la0 v0 + la1 v1 + la2 v2 along x, then acc += w * s
+template <typename T>
+__device__ __forceinline__ T row3(const T *la, T v0, T v1, T v2)
+{
+    return fma_t(la[2], v2, fma_t(la[1], v1, la[0] * v0));
+}
+
+// ---------------------------------------------------------------------------
 // 1D quadratic Lagrange basis on the nodes {0, 1/2, 1} and its derivative
 // ---------------------------------------------------------------------------
 template <typename T> __device__ __forceinline__ void lag3(T t, T l[3])
 {
-    l[0] = (T(1) - t) * (T(1) - T(2) * t);
-    l[1] = T(4) * t * (T(1) - t);
-    l[2] = t * (T(2) * t - T(1));
+    const T u = T(1) - t;
+    l[0] = u * fma_t(T(-2), t, T(1));
+    l[1] = (T(4) * t) * u;
+    l[2] = t * fma_t(T(2), t, T(-1));
 }
 template <typename T> __device__ __forceinline__ void dlag3(T t, T d[3])
 {
@@ -148,10 +164,8 @@ __device__ __forceinline__ void eval_q2(const MeshDev &m, const typename NodeVec
             for (int b = 0; b < 3; ++b) {
                 const auto *row = base + (int64_t)m.nnx * b;
                 auto v0 = row[0], v1 = row[1], v2 = row[2];
-                T s0 = la[0] * v0.x + la[1] * v1.x + la[2] * v2.x;
-                T s1 = la[0] * v0.y + la[1] * v1.y + la[2] * v2.y;
-                a0 += lb[b] * s0;
-                a1 += lb[b] * s1;
+                a0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), a0);
+                a1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), a1);
             }
         }
         u[0] = (double)a0;
@@ -180,16 +194,13 @@ __device__ __forceinline__ void eval_q2(const MeshDev &m, const typename NodeVec
                     v1 = row[1];
                     v2 = row[2];
                 }
-                T s0 = la[0] * v0.x + la[1] * v1.x + la[2] * v2.x;
-                T s1 = la[0] * v0.y + la[1] * v1.y + la[2] * v2.y;
-                T s2 = la[0] * v0.z + la[1] * v1.z + la[2] * v2.z;
-                r0 += lb[b] * s0;
-                r1 += lb[b] * s1;
-                r2 += lb[b] * s2;
+                r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
+                r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
+                r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
             }
-            a0 += lc[c] * r0;
-            a1 += lc[c] * r1;
-            a2 += lc[c] * r2;
+            a0 = fma_t(lc[c], r0, a0);
+            a1 = fma_t(lc[c], r1, a1);
+            a2 = fma_t(lc[c], r2, a2);
         }
         u[0] = (double)a0;
         u[1] = (double)a1;
@@ -302,8 +313,8 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
         for (int b = 0; b < 3; ++b) {
             const int r = base + nnx * b;
             const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
-            a0 += lb[b] * (la[0] * v0.x + la[1] * v1.x + la[2] * v2.x);
-            a1 += lb[b] * (la[0] * v0.y + la[1] * v1.y + la[2] * v2.y);
+            a0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), a0);
+            a1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), a1);
         }
         u[0] = (double)a0;
         u[1] = (double)a1;
@@ -320,13 +331,13 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
             for (int b = 0; b < 3; ++b) {
                 const int r = base + nnx * b + sz * c;
                 const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
-                r0 += lb[b] * (la[0] * v0.x + la[1] * v1.x + la[2] * v2.x);
-                r1 += lb[b] * (la[0] * v0.y + la[1] * v1.y + la[2] * v2.y);
-                r2 += lb[b] * (la[0] * v0.z + la[1] * v1.z + la[2] * v2.z);
+                r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
+                r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
+                r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
             }
-            a0 += lc[c] * r0;
-            a1 += lc[c] * r1;
-            a2 += lc[c] * r2;
+            a0 = fma_t(lc[c], r0, a0);
+            a1 = fma_t(lc[c], r1, a1);
+            a2 = fma_t(lc[c], r2, a2);
         }
         u[0] = (double)a0;
         u[1] = (double)a1;

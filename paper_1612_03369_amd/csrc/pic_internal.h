@@ -29,6 +29,12 @@ struct WorkItem {
     int32_t problem;
     int32_t c0, c1;          // cells [c0, c1)
 };
+// Block of cells [i0, i0+BX) x [j0, j0+BY) x [k0, k0+BZ) of a uniform mesh
+// (clipped to the mesh); its particles are BY*BZ runs of consecutive cells.
+struct BlockItem {
+    int32_t problem;
+    int32_t i0, j0, k0;
+};
 struct ScanItem {
     int32_t problem;
     int32_t chunk;

@@ -225,6 +225,255 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
 }
 
 // ===========================================================================
+// advect + locate on uniform meshes with the field of a block of cells staged
+// in LDS
+// ===========================================================================
+// Block geometry: BX x BY x BZ cells, LDS window = the Q2 nodes of the block
+// plus one cell on every side, (2BX+5) x (2BY+5) x (2BZ+5) node values.
+template <int D, int BX, int BY, int BZ> struct BlockShape {
+    static constexpr int WX = 2 * BX + 5;
+    static constexpr int WY = 2 * BY + 5;
+    static constexpr int WZ = D == 3 ? 2 * BZ + 5 : 1;
+    static constexpr int NODES = WX * WY * WZ;
+    static constexpr int CELLS = BX * BY * (D == 3 ? BZ : 1);
+    static constexpr int ROWS = BY * (D == 3 ? BZ : 1);
+};
+
+// Q2 evaluation from the LDS window; (lx, ly, lz) = window index of local node (0,0,0).
+template <int D, typename T, int WX, int WY>
+__device__ __forceinline__ void eval_q2_lds(const typename NodeVec<D, T>::type *W, int lx, int ly, int lz,
+                                            const double *tr, double *u)
+{
+    T la[3], lb[3];
+    lag3((T)tr[0], la);
+    lag3((T)tr[1], lb);
+    if constexpr (D == 2) {
+        const auto *base = W + lx + WX * ly;
+        T a0 = 0, a1 = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const auto *r = base + WX * b;
+            const auto v0 = r[0], v1 = r[1], v2 = r[2];
+            a0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), a0);
+            a1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), a1);
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+    } else {
+        T lc[3];
+        lag3((T)tr[2], lc);
+        const auto *base = W + lx + WX * (ly + WY * lz);
+        T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const auto *r = base + WX * (b + WY * c);
+                const auto v0 = r[0], v1 = r[1], v2 = r[2];
+                r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
+                r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
+                r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
+            }
+            a0 = fma_t(lc[c], r0, a0);
+            a1 = fma_t(lc[c], r1, a1);
+            a2 = fma_t(lc[c], r2, a2);
+        }
+        u[0] = (double)a0;
+        u[1] = (double)a1;
+        u[2] = (double)a2;
+    }
+}
+
+// Field at the reference point t of cell ijk: from the LDS window when the
+// cell lies in the block or its one-cell halo, else from global memory.
+template <int D, typename T, int BX, int BY, int BZ>
+__device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> U,
+                                         const typename NodeVec<D, T>::type *W, const int *b0, const int ijk[3],
+                                         const double *t, double *u)
+{
+    using Sh = BlockShape<D, BX, BY, BZ>;
+    const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;
+    bool in = ((unsigned)di < (unsigned)(BX + 2)) & ((unsigned)dj < (unsigned)(BY + 2));
+    if constexpr (D == 3) in &= (unsigned)dk < (unsigned)(BZ + 2);
+    if (in) eval_q2_lds<D, T, Sh::WX, Sh::WY>(W, 2 * di, 2 * dj, D == 3 ? 2 * dk : 0, t, u);
+    else eval_q2_ijk<D, T>(U, m.nnx, m.nny, ijk, t, u);
+}
+
+template <int D, int S, typename T, int BX, int BY, int BZ>
+__device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> U,
+                                                   const typename NodeVec<D, T>::type *W, const int *b0, double dt,
+                                                   double *x, double *t, uint32_t K, bool &near)
+{
+    int ijk[3], jk[3];
+    double u[3], k1[3], y[3], ty[3], xn[3];
+    ijk_of<D>(m, K, ijk);
+    eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, ijk, t, u);
+#pragma unroll
+    for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
+    bool in = true;
+    if constexpr (S == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a];
+    } else if constexpr (S == 2) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
+    } else {
+        double k2[3], k3[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k2[a] = dt * u[a];
+            y[a] = x[a] + 0.5 * k2[a];
+        }
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k3[a] = dt * u[a];
+            y[a] = x[a] + k3[a];
+        }
+        near |= near_boundary<D>(m, y);
+        in &= locate_uniform<D>(m, y, jk, ty);
+        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+        const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
+    }
+    near |= near_boundary<D>(m, xn);
+    double tn[3];
+    in &= locate_uniform<D>(m, xn, jk, tn);
+    if (!in) return LOST;
+    near |= face_dist<D>(tn) < NEAR_TOL;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = xn[a];
+        t[a] = tn[a];
+    }
+    return cell_of<D>(m, jk);
+}
+
+/*
+ * Work item = block of cells of a uniform mesh.  The workgroup copies the
+ * block's Q2 node values plus a one-cell halo into LDS once, then advances
+ * every particle of the block's cells; stage points in the halo read LDS, the
+ * rare ones farther away read global memory.  Outputs as k_advect.
+ */
+template <int D, int S, typename T, int BX, int BY, int BZ>
+__global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const ProblemDev *__restrict__ probs,
+                                                      const BlockItem *__restrict__ work, int n_work)
+{
+    using Sh = BlockShape<D, BX, BY, BZ>;
+    using V = typename NodeVec<D, T>::type;
+    __shared__ V s_w[Sh::NODES];
+    __shared__ int s_cnt[Sh::CELLS];
+    __shared__ int s_pre[Sh::ROWS + 1];
+    __shared__ int s_beg[Sh::ROWS];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const BlockItem bi = work[w];
+        const ProblemDev &P = probs[bi.problem];
+        const MeshDev &m = P.mesh;
+        const StoreDev cur = P.store[P.cur];
+        const int64_t cap = P.cap;
+        const double dt = P.dt;
+        auto U = (gptr<V>)(sizeof(T) == 4 ? P.u32 : P.u64);
+        const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
+        const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
+        const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
+        // stage the window: node (wx, wy, wz) = global node 2*b0 - 2 + w
+        const int gx0 = 2 * bi.i0 - 2, gy0 = 2 * bi.j0 - 2, gz0 = D == 3 ? 2 * bi.k0 - 2 : 0;
+        const int gzn = D == 3 ? 2 * m.n[2] : 0;
+        for (int q = threadIdx.x; q < Sh::NODES; q += BLOCK) {
+            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
+            const int gx = gx0 + wx, gy = gy0 + wy, gz = gz0 + wz;
+            if (gx >= 0 && gx <= 2 * m.n[0] && gy >= 0 && gy <= 2 * m.n[1] && gz >= 0 && gz <= gzn)
+                s_w[q] = U[gx + m.nnx * (gy + m.nny * gz)];
+        }
+        for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) s_cnt[q] = 0;
+        if (threadIdx.x < 64) {
+            // particle runs of the block's rows and their prefix
+            int r = threadIdx.x, len = 0, beg = 0;
+            if (r < Sh::ROWS) {
+                const int rj = r % BY, rk = r / BY;
+                if (rj < ny && rk < nz) {
+                    const int K = bi.i0 + m.n[0] * ((bi.j0 + rj) + m.n[1] * (D == 3 ? bi.k0 + rk : 0));
+                    beg = cur.cs[K];
+                    len = cur.cs[K + nx] - beg;
+                }
+                s_beg[r] = beg;
+            }
+            int inc = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                int v = __shfl_up(inc, o, 64);
+                if ((threadIdx.x & 63) >= o) inc += v;
+            }
+            if (r < Sh::ROWS) s_pre[r + 1] = inc;
+            if (r == 0) s_pre[0] = 0;
+        }
+        __syncthreads();
+        const int total = s_pre[Sh::ROWS];
+        int st_lost = 0, st_moved = 0, st_near = 0;
+        for (int f = threadIdx.x; f < total; f += BLOCK) {
+            int r = 0;
+#pragma unroll
+            for (int step = Sh::ROWS / 2; step >= 1; step >>= 1)
+                if (r + step < Sh::ROWS && s_pre[r + step] <= f) r += step;
+            const int i = s_beg[r] + (f - s_pre[r]);
+            const int32_t K = cur.cell[i];
+            double x[3], t[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                x[a] = cur.x[a * cap + i];
+                t[a] = cur.xr[a * cap + i];
+            }
+            bool near = false;
+            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, U, s_w, b0, dt, x, t, (uint32_t)K, near);
+            if (key != LOST) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    cur.x[a * cap + i] = x[a];
+                    cur.xr[a * cap + i] = t[a];
+                }
+            }
+            P.scr.key[i] = key;
+            const bool stay = key == (uint32_t)K;
+            if (stay) {
+                int ijk[3];
+                ijk_of<D>(m, (uint32_t)K, ijk);
+                atomicAdd(&s_cnt[(ijk[0] - bi.i0) + BX * ((ijk[1] - bi.j0) + BY * (D == 3 ? ijk[2] - bi.k0 : 0))], 1);
+            } else if (key != LOST) {
+                atomicAdd(&P.scr.n_arrive[key], 1);
+            }
+            st_lost += key == LOST;
+            st_moved += (key != LOST) && !stay;
+            st_near += near;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) {
+            const int ci = q % BX, cj = (q / BX) % BY, ck = q / (BX * BY);
+            if (ci < nx && cj < ny && ck < nz)
+                P.scr.n_stay[(bi.i0 + ci) + m.n[0] * ((bi.j0 + cj) + m.n[1] * (D == 3 ? bi.k0 + ck : 0))] = s_cnt[q];
+        }
+        flush_stats(P.scr.stats, ST_PSTEPS, threadIdx.x == 0 ? total : 0, nullptr);
+        flush_stats(P.scr.stats, ST_LOST, st_lost, nullptr);
+        flush_stats(P.scr.stats, ST_MOVED, st_moved, nullptr);
+        flush_stats(P.scr.stats, ST_NEAR, st_near, nullptr);
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
 // scan of the new per-cell counts (three phases over chunks of cells)
 // ===========================================================================
 constexpr int SCAN_PER_THREAD = 8;
