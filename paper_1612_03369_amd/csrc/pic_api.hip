@@ -44,6 +44,8 @@ struct pic_ctx {
     std::vector<int32_t> h_anchor;
     // field
     void *u64 = nullptr, *u32 = nullptr;
+    double *c64 = nullptr;            // uniform meshes: monomial coefficients per cell
+    float *c32 = nullptr;
     bool have_field = false;
     // store
     bool bound = false;
@@ -177,7 +179,11 @@ void free_mesh(pic_ctx *c)
     c->mesh_allocs.clear();
     if (c->u64) hipFree(c->u64);
     if (c->u32) hipFree(c->u32);
+    if (c->c64) hipFree(c->c64);
+    if (c->c32) hipFree(c->c32);
     c->u64 = c->u32 = nullptr;
+    c->c64 = nullptr;
+    c->c32 = nullptr;
     c->have_mesh = false;
     c->node_xyz.clear();
     c->node_hanging.clear();
@@ -248,8 +254,11 @@ pic_status upload_problem(pic_ctx *c)
 #define PIC_USE_BLOCK_ADVECT 1
 #endif
 // Cell-block shapes of the LDS-staged advect (uniform meshes) per (dim, precision).
-constexpr int BLK3_F32[3] = {4, 4, 4};
-constexpr int BLK3_F64[3] = {4, 4, 2};
+#ifndef PIC_BLK3_F32
+#define PIC_BLK3_F32 4, 4, 4
+#endif
+constexpr int BLK3_F32[3] = {PIC_BLK3_F32};
+constexpr int BLK3_F64[3] = {4, 2, 2};
 constexpr int BLK2[3] = {8, 8, 1};
 inline const int *block_shape(int dim, int prec)
 {
@@ -630,9 +639,26 @@ extern "C" pic_status pic_set_velocity(pic_ctx *c, const void *U, int prec)
         s = resolve_hanging(c);
         if (s) return s;
     }
+    if (c->mesh.kind == MESH_UNIFORM) {
+        const int stride = d == 3 ? Mono<3>::STRIDE : Mono<2>::STRIDE;
+        const size_t nco = (size_t)stride * (size_t)c->mesh.n_cells;
+        if (!c->c64) {
+            if ((s = dalloc(c, &c->c64, nco))) return s;
+            if ((s = dalloc(c, &c->c32, nco))) return s;
+        }
+        unsigned gc = (unsigned)((c->mesh.n_cells + BLOCK - 1) / BLOCK);
+        if (d == 3)
+            hipLaunchKernelGGL(k_mono_coeffs<3>, dim3(gc), dim3(BLOCK), 0, c->stream, c->mesh, (const void *)c->u64, c->c64, c->c32);
+        else
+            hipLaunchKernelGGL(k_mono_coeffs<2>, dim3(gc), dim3(BLOCK), 0, c->stream, c->mesh, (const void *)c->u64, c->c64, c->c32);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     c->have_field = true;
     c->h_prob.u64 = c->u64;
     c->h_prob.u32 = c->u32;
+    c->h_prob.c64 = c->c64;
+    c->h_prob.c32 = c->c32;
     if (c->bound) return upload_problem(c);
     return PIC_OK;
 }
@@ -675,6 +701,8 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     P.dt = 0.0;
     P.u64 = c->u64;
     P.u32 = c->u32;
+    P.c64 = c->c64;
+    P.c32 = c->c32;
     P.scr = c->scr;
     c->last_dt = 0.0;
     // zeroed state: empty buffers, zero counters

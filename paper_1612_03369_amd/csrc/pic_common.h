@@ -346,6 +346,79 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
 }
 
 // ---------------------------------------------------------------------------
+// monomial (power) form of the Q2 field per cell: on the reference cell
+//   u_c(t) = sum_{a,b,c} C[comp][c][b][a] t0^a t1^b t2^c,
+// obtained from the nodal values by the 1D change of basis
+//   (U0, U1, U2) -> (U0, -3 U0 + 4 U1 - U2, 2 U0 - 4 U1 + 2 U2)
+// along each axis; evaluated by nested Horner steps (26 FMA per component
+// in 3D).  Cells are stored with a padded stride (84 values in 3D, 20 in 2D)
+// that keeps 16-byte alignment and spreads neighbouring cells over the LDS
+// banks.
+// ---------------------------------------------------------------------------
+template <int D> struct Mono {
+    static constexpr int NCOEF = D == 3 ? 27 : 9;
+    static constexpr int STRIDE = D == 3 ? 84 : 20;
+};
+
+template <int D, typename T, typename Ptr>
+__device__ __forceinline__ void eval_mono(Ptr C, const double *tr, double *u)
+{
+    const T t0 = (T)tr[0], t1 = (T)tr[1];
+    if constexpr (D == 2) {
+#pragma unroll
+        for (int comp = 0; comp < 2; ++comp) {
+            const auto *c = C + comp * 9;
+            T r[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) r[b] = fma_t(t0, fma_t(t0, (T)c[3 * b + 2], (T)c[3 * b + 1]), (T)c[3 * b]);
+            u[comp] = (double)fma_t(t1, fma_t(t1, r[2], r[1]), r[0]);
+        }
+    } else {
+        const T t2 = (T)tr[2];
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            const auto *c = C + comp * 27;
+            T pl[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                T r[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int o = 9 * cc + 3 * b;
+                    r[b] = fma_t(t0, fma_t(t0, (T)c[o + 2], (T)c[o + 1]), (T)c[o]);
+                }
+                pl[cc] = fma_t(t1, fma_t(t1, r[2], r[1]), r[0]);
+            }
+            u[comp] = (double)fma_t(t2, fma_t(t2, pl[2], pl[1]), pl[0]);
+        }
+    }
+}
+
+// Stage-point location on a uniform mesh: cell and reference coordinates from
+// s = (y - lo)/h; inside = 0 <= s <= n per axis; near = within 1e-10 of the
+// domain boundary.  Reference coordinates s - i are accurate to a few ulps of
+// s, which only feeds the field evaluation; stored locations use
+// locate_uniform.
+template <int D>
+__device__ __forceinline__ bool locate_stage(const MeshDev &m, const double *y, int ijk[3], double *t, bool &near)
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double s = (y[a] - m.lo[a]) * m.inv_h[a];
+        const double n = (double)m.n[a];
+        inside &= (s >= 0.0) & (s <= n);
+        near |= (s < NEAR_TOL) | (s > n - NEAR_TOL);
+        int i = (int)floor(s);
+        i = i >= m.n[a] ? m.n[a] - 1 : (i < 0 ? 0 : i);
+        t[a] = s - (double)i;
+        ijk[a] = i;
+    }
+    if constexpr (D == 2) ijk[2] = 0;
+    return inside;
+}
+
+// ---------------------------------------------------------------------------
 // cell maps
 // ---------------------------------------------------------------------------
 // Axis-aligned box of a uniform or octree cell.

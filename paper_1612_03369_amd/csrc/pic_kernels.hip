@@ -228,87 +228,43 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
 // advect + locate on uniform meshes with the field of a block of cells staged
 // in LDS
 // ===========================================================================
-// Block geometry: BX x BY x BZ cells, LDS window = the Q2 nodes of the block
-// plus one cell on every side, (2BX+5) x (2BY+5) x (2BZ+5) node values.
+// Block of BX x BY x BZ cells; the LDS window holds the monomial coefficients
+// of the block's cells plus a one-cell halo, (BX+2) x (BY+2) x (BZ+2) cells.
 template <int D, int BX, int BY, int BZ> struct BlockShape {
-    static constexpr int WX = 2 * BX + 5;
-    static constexpr int WY = 2 * BY + 5;
-    static constexpr int WZ = D == 3 ? 2 * BZ + 5 : 1;
-    static constexpr int NODES = WX * WY * WZ;
+    static constexpr int CX = BX + 2;
+    static constexpr int CY = BY + 2;
+    static constexpr int CZ = D == 3 ? BZ + 2 : 1;
+    static constexpr int WCELLS = CX * CY * CZ;
     static constexpr int CELLS = BX * BY * (D == 3 ? BZ : 1);
     static constexpr int ROWS = BY * (D == 3 ? BZ : 1);
 };
 
-// Q2 evaluation from the LDS window; (lx, ly, lz) = window index of local node (0,0,0).
-template <int D, typename T, int WX, int WY>
-__device__ __forceinline__ void eval_q2_lds(const typename NodeVec<D, T>::type *W, int lx, int ly, int lz,
-                                            const double *tr, double *u)
-{
-    T la[3], lb[3];
-    lag3((T)tr[0], la);
-    lag3((T)tr[1], lb);
-    if constexpr (D == 2) {
-        const auto *base = W + lx + WX * ly;
-        T a0 = 0, a1 = 0;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const auto *r = base + WX * b;
-            const auto v0 = r[0], v1 = r[1], v2 = r[2];
-            a0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), a0);
-            a1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), a1);
-        }
-        u[0] = (double)a0;
-        u[1] = (double)a1;
-    } else {
-        T lc[3];
-        lag3((T)tr[2], lc);
-        const auto *base = W + lx + WX * (ly + WY * lz);
-        T a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T r0 = 0, r1 = 0, r2 = 0;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const auto *r = base + WX * (b + WY * c);
-                const auto v0 = r[0], v1 = r[1], v2 = r[2];
-                r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
-                r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
-                r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
-            }
-            a0 = fma_t(lc[c], r0, a0);
-            a1 = fma_t(lc[c], r1, a1);
-            a2 = fma_t(lc[c], r2, a2);
-        }
-        u[0] = (double)a0;
-        u[1] = (double)a1;
-        u[2] = (double)a2;
-    }
-}
-
 // Field at the reference point t of cell ijk: from the LDS window when the
-// cell lies in the block or its one-cell halo, else from global memory.
+// cell lies in the block or its halo, else from the global coefficient array.
 template <int D, typename T, int BX, int BY, int BZ>
-__device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> U,
-                                         const typename NodeVec<D, T>::type *W, const int *b0, const int ijk[3],
+__device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<T> Cg, const T *W, const int *b0, const int ijk[3],
                                          const double *t, double *u)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
     const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;
-    bool in = ((unsigned)di < (unsigned)(BX + 2)) & ((unsigned)dj < (unsigned)(BY + 2));
-    if constexpr (D == 3) in &= (unsigned)dk < (unsigned)(BZ + 2);
-    if (in) eval_q2_lds<D, T, Sh::WX, Sh::WY>(W, 2 * di, 2 * dj, D == 3 ? 2 * dk : 0, t, u);
-    else eval_q2_ijk<D, T>(U, m.nnx, m.nny, ijk, t, u);
+    bool in = ((unsigned)di < (unsigned)Sh::CX) & ((unsigned)dj < (unsigned)Sh::CY);
+    if constexpr (D == 3) in &= (unsigned)dk < (unsigned)Sh::CZ;
+    if (in) {
+        eval_mono<D, T>(W + (di + Sh::CX * (dj + Sh::CY * (D == 3 ? dk : 0))) * Mono<D>::STRIDE, t, u);
+    } else {
+        const int64_t K = cell_of<D>(m, ijk);
+        eval_mono<D, T>(Cg + K * Mono<D>::STRIDE, t, u);
+    }
 }
 
 template <int D, int S, typename T, int BX, int BY, int BZ>
-__device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> U,
-                                                   const typename NodeVec<D, T>::type *W, const int *b0, double dt,
+__device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<T> Cg, const T *W, const int *b0, double dt,
                                                    double *x, double *t, uint32_t K, bool &near)
 {
     int ijk[3], jk[3];
     double u[3], k1[3], y[3], ty[3], xn[3];
     ijk_of<D>(m, K, ijk);
-    eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, ijk, t, u);
+    eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, ijk, t, u);
 #pragma unroll
     for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
     bool in = true;
@@ -318,34 +274,30 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typena
     } else if constexpr (S == 2) {
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
-        near |= near_boundary<D>(m, y);
-        in &= locate_uniform<D>(m, y, jk, ty);
-        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
     } else {
         double k2[3], k3[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
-        near |= near_boundary<D>(m, y);
-        in &= locate_uniform<D>(m, y, jk, ty);
-        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             k2[a] = dt * u[a];
             y[a] = x[a] + 0.5 * k2[a];
         }
-        near |= near_boundary<D>(m, y);
-        in &= locate_uniform<D>(m, y, jk, ty);
-        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             k3[a] = dt * u[a];
             y[a] = x[a] + k3[a];
         }
-        near |= near_boundary<D>(m, y);
-        in &= locate_uniform<D>(m, y, jk, ty);
-        eval_blk<D, T, BX, BY, BZ>(m, U, W, b0, jk, ty, u);
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
         const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
@@ -365,17 +317,19 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typena
 
 /*
  * Work item = block of cells of a uniform mesh.  The workgroup copies the
- * block's Q2 node values plus a one-cell halo into LDS once, then advances
- * every particle of the block's cells; stage points in the halo read LDS, the
- * rare ones farther away read global memory.  Outputs as k_advect.
+ * monomial coefficients of the block's cells plus a one-cell halo into LDS
+ * once, then advances every particle of the block's cells; stage points in
+ * the halo read LDS, the rare ones farther away read global memory.  Outputs
+ * as k_advect.
  */
 template <int D, int S, typename T, int BX, int BY, int BZ>
 __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const ProblemDev *__restrict__ probs,
-                                                      const BlockItem *__restrict__ work, int n_work)
+                                                                      const BlockItem *__restrict__ work, int n_work)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
-    using V = typename NodeVec<D, T>::type;
-    __shared__ V s_w[Sh::NODES];
+    constexpr int STRIDE = Mono<D>::STRIDE;
+    constexpr int CHUNKS = STRIDE * (int)sizeof(T) / 16;       // 16-byte pieces per cell
+    __shared__ __attribute__((aligned(16))) T s_w[Sh::WCELLS * STRIDE];
     __shared__ int s_cnt[Sh::CELLS];
     __shared__ int s_pre[Sh::ROWS + 1];
     __shared__ int s_beg[Sh::ROWS];
@@ -386,23 +340,26 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         const StoreDev cur = P.store[P.cur];
         const int64_t cap = P.cap;
         const double dt = P.dt;
-        auto U = (gptr<V>)(sizeof(T) == 4 ? P.u32 : P.u64);
+        auto Cg = (gptr<T>)(sizeof(T) == 4 ? (const void *)P.c32 : (const void *)P.c64);
         const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
         const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
         const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
-        // stage the window: node (wx, wy, wz) = global node 2*b0 - 2 + w
-        const int gx0 = 2 * bi.i0 - 2, gy0 = 2 * bi.j0 - 2, gz0 = D == 3 ? 2 * bi.k0 - 2 : 0;
-        const int gzn = D == 3 ? 2 * m.n[2] : 0;
-        for (int q = threadIdx.x; q < Sh::NODES; q += BLOCK) {
-            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
-            const int gx = gx0 + wx, gy = gy0 + wy, gz = gz0 + wz;
-            if (gx >= 0 && gx <= 2 * m.n[0] && gy >= 0 && gy <= 2 * m.n[1] && gz >= 0 && gz <= gzn)
-                s_w[q] = U[gx + m.nnx * (gy + m.nny * gz)];
+        // stage the window: window cell (wx, wy, wz) = mesh cell b0 - 1 + w
+        for (int q = threadIdx.x; q < Sh::WCELLS * CHUNKS; q += BLOCK) {
+            const int wc = q / CHUNKS, ch = q - wc * CHUNKS;
+            const int wx = wc % Sh::CX, wy = (wc / Sh::CX) % Sh::CY, wz = wc / (Sh::CX * Sh::CY);
+            const int ci = bi.i0 - 1 + wx, cj = bi.j0 - 1 + wy, ck = D == 3 ? bi.k0 - 1 + wz : 0;
+            if (ci >= 0 && ci < m.n[0] && cj >= 0 && cj < m.n[1] && ck >= 0 && ck < (D == 3 ? m.n[2] : 1)) {
+                const int64_t K = ci + (int64_t)m.n[0] * (cj + (int64_t)m.n[1] * ck);
+                const float4 v = ((gptr<float4>)(Cg + K * STRIDE))[ch];
+                reinterpret_cast<float4 *>(s_w + wc * STRIDE)[ch] = v;
+            }
         }
         for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) s_cnt[q] = 0;
         if (threadIdx.x < 64) {
             // particle runs of the block's rows and their prefix
-            int r = threadIdx.x, len = 0, beg = 0;
+            const int r = threadIdx.x;
+            int len = 0, beg = 0;
             if (r < Sh::ROWS) {
                 const int rj = r % BY, rk = r / BY;
                 if (rj < ny && rk < nz) {
@@ -415,8 +372,8 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
             int inc = len;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
-                int v = __shfl_up(inc, o, 64);
-                if ((threadIdx.x & 63) >= o) inc += v;
+                const int v = __shfl_up(inc, o, 64);
+                if (r >= o) inc += v;
             }
             if (r < Sh::ROWS) s_pre[r + 1] = inc;
             if (r == 0) s_pre[0] = 0;
@@ -424,21 +381,48 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         __syncthreads();
         const int total = s_pre[Sh::ROWS];
         int st_lost = 0, st_moved = 0, st_near = 0;
-        for (int f = threadIdx.x; f < total; f += BLOCK) {
-            int r = 0;
+        // particle f of the block -> its row and store index
+        auto locate_f = [&](int f, int &r) {
+            r = 0;
 #pragma unroll
             for (int step = Sh::ROWS / 2; step >= 1; step >>= 1)
                 if (r + step < Sh::ROWS && s_pre[r + step] <= f) r += step;
-            const int i = s_beg[r] + (f - s_pre[r]);
-            const int32_t K = cur.cell[i];
+            return s_beg[r] + (f - s_pre[r]);
+        };
+        // one-deep software prefetch of the next particle's state hides the
+        // HBM latency that the few resident waves cannot
+        int rn = 0, in_ = 0;
+        int32_t Kn = 0;
+        double xn_[3] = {0, 0, 0}, tn_[3] = {0, 0, 0};
+        if ((int)threadIdx.x < total) {
+            in_ = locate_f(threadIdx.x, rn);
+            Kn = cur.cell[in_];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xn_[a] = cur.x[a * cap + in_];
+                tn_[a] = cur.xr[a * cap + in_];
+            }
+        }
+        for (int f = threadIdx.x; f < total; f += BLOCK) {
+            const int r = rn, i = in_;
+            const int32_t K = Kn;
             double x[3], t[3];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                x[a] = cur.x[a * cap + i];
-                t[a] = cur.xr[a * cap + i];
+                x[a] = xn_[a];
+                t[a] = tn_[a];
+            }
+            if (f + BLOCK < total) {
+                in_ = locate_f(f + BLOCK, rn);
+                Kn = cur.cell[in_];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    xn_[a] = cur.x[a * cap + in_];
+                    tn_[a] = cur.xr[a * cap + in_];
+                }
             }
             bool near = false;
-            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, U, s_w, b0, dt, x, t, (uint32_t)K, near);
+            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Cg, s_w, b0, dt, x, t, (uint32_t)K, near);
             if (key != LOST) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
@@ -449,9 +433,9 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
             P.scr.key[i] = key;
             const bool stay = key == (uint32_t)K;
             if (stay) {
-                int ijk[3];
-                ijk_of<D>(m, (uint32_t)K, ijk);
-                atomicAdd(&s_cnt[(ijk[0] - bi.i0) + BX * ((ijk[1] - bi.j0) + BY * (D == 3 ? ijk[2] - bi.k0 : 0))], 1);
+                // cell (i0 + ci, j0 + r % BY, k0 + r / BY) of row r
+                const int ci = K - (bi.i0 + m.n[0] * ((bi.j0 + r % BY) + m.n[1] * (D == 3 ? bi.k0 + r / BY : 0)));
+                atomicAdd(&s_cnt[ci + BX * r], 1);
             } else if (key != LOST) {
                 atomicAdd(&P.scr.n_arrive[key], 1);
             }
@@ -461,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         }
         __syncthreads();
         for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) {
-            const int ci = q % BX, cj = (q / BX) % BY, ck = q / (BX * BY);
+            const int ci = q % BX, r = q / BX, cj = r % BY, ck = r / BY;
             if (ci < nx && cj < ny && ck < nz)
                 P.scr.n_stay[(bi.i0 + ci) + m.n[0] * ((bi.j0 + cj) + m.n[1] * (D == 3 ? bi.k0 + ck : 0))] = s_cnt[q];
         }
@@ -471,6 +455,71 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         flush_stats(P.scr.stats, ST_NEAR, st_near, nullptr);
         __syncthreads();
     }
+}
+
+// Monomial coefficients of every cell of a structured mesh from the repacked
+// nodal field (double precision), stored in both precisions.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_mono_coeffs(const MeshDev m, const void *u64, double *c64, float *c32)
+{
+    const int64_t K = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (K >= m.n_cells) return;
+    constexpr int NC = Mono<D>::NCOEF, STRIDE = Mono<D>::STRIDE;
+    const double M[3][3] = {{1.0, 0.0, 0.0}, {-3.0, 4.0, -1.0}, {2.0, -4.0, 2.0}};
+    int ijk[3];
+    cell_ijk(m, K, ijk);
+    double out[STRIDE];
+    for (int q = 0; q < STRIDE; ++q) out[q] = 0.0;
+    for (int comp = 0; comp < D; ++comp) {
+        double v[27];
+        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t g = (2 * ijk[0] + a) + (int64_t)m.nnx * ((2 * ijk[1] + b) + (int64_t)m.nny * (2 * ijk[2] + cc));
+                    double val;
+                    if constexpr (D == 3) {
+                        const double4 nv = ((const double4 *)u64)[g];
+                        val = comp == 0 ? nv.x : (comp == 1 ? nv.y : nv.z);
+                    } else {
+                        const double2 nv = ((const double2 *)u64)[g];
+                        val = comp == 0 ? nv.x : nv.y;
+                    }
+                    v[a + 3 * b + 9 * cc] = val;
+                }
+        // change of basis along x, then y, then z
+        double w[27];
+        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    double acc = 0.0;
+                    for (int i = 0; i < 3; ++i) acc += M[a][i] * v[i + 3 * b + 9 * cc];
+                    w[a + 3 * b + 9 * cc] = acc;
+                }
+        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    double acc = 0.0;
+                    for (int i = 0; i < 3; ++i) acc += M[b][i] * w[a + 3 * i + 9 * cc];
+                    v[a + 3 * b + 9 * cc] = acc;
+                }
+        if constexpr (D == 3) {
+            for (int cc = 0; cc < 3; ++cc)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) {
+                        double acc = 0.0;
+                        for (int i = 0; i < 3; ++i) acc += M[cc][i] * v[a + 3 * b + 9 * i];
+                        w[a + 3 * b + 9 * cc] = acc;
+                    }
+            for (int q = 0; q < 27; ++q) out[comp * 27 + q] = w[q];
+        } else {
+            for (int q = 0; q < 9; ++q) out[comp * 9 + q] = v[q];
+        }
+    }
+    for (int q = 0; q < STRIDE; ++q) {
+        c64[K * STRIDE + q] = out[q];
+        c32[K * STRIDE + q] = (float)out[q];
+    }
+    (void)NC;
 }
 
 // ===========================================================================
