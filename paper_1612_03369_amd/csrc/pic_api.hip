@@ -210,7 +210,7 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
     char *arr = take(4 * (size_t)nc);
     char *cur = take(4 * (size_t)(nc + 1));
     char *chk = take(8 * (size_t)(n_chunks(nc) + 1));
-    char *st = take(8 * ST_COUNT);
+    char *st = take(8 * (size_t)ST_COUNT * STAT_STRIPES);
     char *nid = take(8);
     char *fl = take(16);
     if (s) {
@@ -927,14 +927,18 @@ extern "C" pic_status pic_stats_read(pic_ctx *c, pic_stats *out)
     if (!c || !out) return PIC_EINVAL;
     if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
     hipSetDevice(c->device);
-    unsigned long long st[ST_COUNT];
-    HIPCHK(c, hipMemcpyAsync(st, c->scr.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    std::vector<unsigned long long> stripes((size_t)ST_COUNT * STAT_STRIPES);
+    HIPCHK(c, hipMemcpyAsync(stripes.data(), c->scr.stats, stripes.size() * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, c->stream));
     int32_t cur = 0;
     pic_status s = pic_current_buffer(c, &cur);
     if (s) return s;
     int32_t live = 0;
     HIPCHK(c, hipMemcpyAsync(&live, c->store.cell_start[cur] + c->mesh.n_cells, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    unsigned long long st[ST_COUNT] = {0};
+    for (int q = 0; q < STAT_STRIPES; ++q)
+        for (int k = 0; k < ST_COUNT; ++k) st[k] += stripes[(size_t)q * ST_COUNT + k];
     out->live = live;
     out->lost = (int64_t)st[ST_LOST];
     out->moved = (int64_t)st[ST_MOVED];
@@ -954,7 +958,7 @@ extern "C" pic_status pic_stats_reset(pic_ctx *c)
     if (!c) return PIC_EINVAL;
     if (!c->bound) return fail(c, PIC_ESTATE, "no store bound");
     hipSetDevice(c->device);
-    HIPCHK(c, hipMemsetAsync(c->scr.stats, 0, sizeof(unsigned long long) * ST_COUNT, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.stats, 0, sizeof(unsigned long long) * ST_COUNT * STAT_STRIPES, c->stream));
     return PIC_OK;
 }
 

@@ -27,6 +27,10 @@ enum StatSlot : int {
     ST_LOST = 0, ST_MOVED, ST_NEAR, ST_FIRST_TRY, ST_FALLBACK, ST_NEWTON_FAIL, ST_ADDED, ST_DELETED,
     ST_STEPS, ST_SEARCHED, ST_PSTEPS, ST_COUNT = 16
 };
+// Counters are spread over STAT_STRIPES copies (one 128-byte line each),
+// picked by workgroup index, so that no address sees more than a sliver of
+// the atomics; readers sum the stripes.
+constexpr int STAT_STRIPES = 256;
 
 struct MeshDev {
     int dim, kind;
@@ -67,7 +71,7 @@ struct ScratchDev {
     int32_t *n_arrive;    // [nc]
     int32_t *cursor;      // [nc]
     int64_t *chunk;       // [n_chunks + 1]
-    unsigned long long *stats;  // [ST_COUNT]
+    unsigned long long *stats;  // [STAT_STRIPES][ST_COUNT]
     unsigned long long *next_id;// [1]
     int32_t *flags;       // [4]
 };

@@ -134,12 +134,13 @@ __device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<ty
     return cell_of<D>(m, jk);
 }
 
-// Accumulate per-thread counters into the device statistics (one atomic per
-// counter per workgroup).
-__device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot, int v, int *s_red)
+// Accumulate per-thread counters into the device statistics: wavefront sum,
+// then one atomic per wavefront into the stripe of this workgroup.
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot, int v, int *)
 {
-    int w = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && w) atomicAdd(&stats[slot], (unsigned long long)w);
+    const int w = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && w)
+        atomicAdd(&stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + slot], (unsigned long long)w);
 }
 
 /*
@@ -892,7 +893,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
     }
     P.scr.key[p] = ok ? (uint32_t)K : LOST;
     if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
-    else atomicAdd(&P.scr.stats[ST_LOST], 1ull);
+    else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
     atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);
 }
 
@@ -1142,8 +1143,9 @@ __global__ __launch_bounds__(BLOCK) void k_population(const ProblemDev *__restri
         }
     }
     if (lane == 0) {
-        if (del) atomicAdd(&P.scr.stats[ST_DELETED], (unsigned long long)del);
-        if (add) atomicAdd(&P.scr.stats[ST_ADDED], (unsigned long long)add);
+        unsigned long long *st = P.scr.stats + (blockIdx.x % STAT_STRIPES) * ST_COUNT;
+        if (del) atomicAdd(&st[ST_DELETED], (unsigned long long)del);
+        if (add) atomicAdd(&st[ST_ADDED], (unsigned long long)add);
     }
     (void)psum;
 }
