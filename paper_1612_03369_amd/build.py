@@ -25,7 +25,8 @@ def command(out: str = LIB, extra=()) -> list:
     return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions are kept out of the generated code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-munsafe-fp-atomics", "-fvisibility=hidden",
+            # contraction only within an expression: identical rounding in every kernel
+            "-ffp-contract=on", "-munsafe-fp-atomics", "-fvisibility=hidden",
             "-Wall", "-Wno-unused-value", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
             "-I", os.path.join(HERE, "..", "include"),
             *extra, "-o", out, *[os.path.join(CSRC, s) for s in SOURCES]]

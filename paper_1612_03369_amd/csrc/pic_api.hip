@@ -204,7 +204,8 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
         off += align256(bytes);
         return p;
     };
-    char *key = take(4 * (size_t)cap);
+    char *key0 = take(4 * (size_t)cap);
+    char *key1 = take(4 * (size_t)cap);
     char *src = take(4 * (size_t)cap);
     char *stay = take(4 * (size_t)nc);
     char *arr = take(4 * (size_t)nc);
@@ -214,7 +215,8 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
     char *nid = take(8);
     char *fl = take(16);
     if (s) {
-        s->key = (uint32_t *)key;
+        s->key[0] = (uint32_t *)key0;
+        s->key[1] = (uint32_t *)key1;
         s->src = (int32_t *)src;
         s->n_stay = (int32_t *)stay;
         s->n_arrive = (int32_t *)arr;
@@ -398,30 +400,58 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
 }
 
 using BlockFn = void (*)(const ProblemDev *, const BlockItem *, int);
-template <int D, int S> BlockFn block_for_prec(int prec)
+template <int D, int S, bool F> BlockFn block_for_prec(int prec)
 {
     if constexpr (D == 3) {
-        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2]>;
-        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2]>;
+        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2], F>;
+        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2], F>;
     } else {
-        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1>;
-        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1>;
+        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1, F>;
+        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1, F>;
     }
 }
-template <int D> BlockFn block_for_scheme(int scheme, int prec)
+template <int D, bool F = false> BlockFn block_for_scheme(int scheme, int prec)
 {
     switch (scheme) {
-    case PIC_EULER: return block_for_prec<D, 1>(prec);
-    case PIC_RK2: return block_for_prec<D, 2>(prec);
-    case PIC_RK4: return block_for_prec<D, 4>(prec);
+    case PIC_EULER: return block_for_prec<D, 1, F>(prec);
+    case PIC_RK2: return block_for_prec<D, 2, F>(prec);
+    case PIC_RK4: return block_for_prec<D, 4, F>(prec);
     }
     return nullptr;
+}
+BlockFn block_kernel(int dim, int scheme, int prec, bool fused)
+{
+    if (dim == 2) return fused ? block_for_scheme<2, true>(scheme, prec) : block_for_scheme<2, false>(scheme, prec);
+    return fused ? block_for_scheme<3, true>(scheme, prec) : block_for_scheme<3, false>(scheme, prec);
+}
+
+#ifndef PIC_FUSE_STEPS
+#define PIC_FUSE_STEPS 1
+#endif
+// n steps on a uniform mesh: the first step's advect, then n-1 times
+// (re-sort fused with the next advect), then the last re-sort.  Identical
+// arithmetic to n separate steps.
+pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec, int n)
+{
+    const int pr = prec == PIC_F32;
+    BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false);
+    BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true);
+    LAUNCH(c, "advect", fa, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+    for (int k = 1; k < n; ++k) {
+        pic_status s = enqueue_scan(c, dp, 0);
+        if (s) return s;
+        LAUNCH(c, "place", k_place, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+        LAUNCH(c, "gather_advect", ff, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+        LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, 1);
+    }
+    return enqueue_sort(c, dp, 1);
 }
 
 pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
 {
     if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
-        BlockFn f = c->mesh.dim == 2 ? block_for_scheme<2>(scheme, prec) : block_for_scheme<3>(scheme, prec);
+        BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false);
         const int pr = prec == PIC_F32;
         LAUNCH(c, "advect", f, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
                c->n_blk[pr]);
@@ -849,6 +879,8 @@ extern "C" pic_status pic_advance(pic_ctx *c, double dt, int32_t n_steps, int32_
     if (c->mesh.kind == MESH_OCTREE && c->mesh.dim != 3) return fail(c, PIC_EINVAL, "octree is 3D");
     hipSetDevice(c->device);
     if ((s = set_dt(c, dt))) return s;
+    if (PIC_FUSE_STEPS && PIC_USE_BLOCK_ADVECT && n_steps > 1 && c->mesh.kind == MESH_UNIFORM && c->n_blk[eval_prec == PIC_F32])
+        return enqueue_steps_fused(c, c->d_prob, scheme, eval_prec, n_steps);
     for (int k = 0; k < n_steps; ++k)
         if ((s = enqueue_step(c, c->d_prob, scheme, eval_prec))) return s;
     return PIC_OK;
@@ -983,7 +1015,7 @@ extern "C" pic_status pic_profile_read(pic_ctx *c, const char *kernel, double *t
         if (launches) *launches = 0;
         static const char *known[] = {"advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip",
                                       "seed", "seed_positions", "population", "population_finish", "interp_average",
-                                      "interp_lls", "adjoint_step", "adjoint_save", "batch_advect"};
+                                      "interp_lls", "adjoint_step", "adjoint_save", "batch_advect", "gather_advect"};
         for (const char *k : known)
             if (!std::strcmp(k, kernel)) return PIC_OK;
         return fail(c, PIC_EINVAL, "unknown kernel name %s", kernel);

@@ -65,7 +65,7 @@ struct StoreDev {
 
 // Per-context scratch (carved out of the caller's workspace).
 struct ScratchDev {
-    uint32_t *key;        // [cap] new cell or LOST
+    uint32_t *key[2];     // [cap] per buffer: new cell (or LOST) of the particle at that position
     int32_t *src;         // [cap] gather source of each destination slot
     int32_t *n_stay;      // [nc]
     int32_t *n_arrive;    // [nc]

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
                     cur.xr[a * cap + i] = t[a];
                 }
             }
-            P.scr.key[i] = key;
+            P.scr.key[P.cur][i] = key;
             const bool stay = key == (uint32_t)K;
             if (stay) atomicAdd(&s_cnt[K - c0], 1);
             else if (key != LOST) atomicAdd(&P.scr.n_arrive[key], 1);
@@ -320,10 +320,18 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<T> Cg,
  * Work item = block of cells of a uniform mesh.  The workgroup copies the
  * monomial coefficients of the block's cells plus a one-cell halo into LDS
  * once, then advances every particle of the block's cells; stage points in
- * the halo read LDS, the rare ones farther away read global memory.  Outputs
- * as k_advect.
+ * the halo read LDS, the rare ones farther away read global memory.
+ *
+ * FUSED = false: the particles are those of the current buffer; new location,
+ * reference location and key are written in place (as k_advect).
+ * FUSED = true: the particles are the destination slots p of the re-sort in
+ * progress (cells of the other buffer, whose cell_start the scan produced);
+ * slot p takes particle src[p] of the current buffer, advances it by the next
+ * step and writes it, its id, properties, cell and new key to the other
+ * buffer.  A fused step is thus "finish the previous step's permutation and
+ * compute the next step's keys" in one pass over the particle state.
  */
-template <int D, int S, typename T, int BX, int BY, int BZ>
+template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED>
 __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const ProblemDev *__restrict__ probs,
                                                                       const BlockItem *__restrict__ work, int n_work)
 {
@@ -339,6 +347,9 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         const ProblemDev &P = probs[bi.problem];
         const MeshDev &m = P.mesh;
         const StoreDev cur = P.store[P.cur];
+        const StoreDev out = P.store[FUSED ? 1 - P.cur : P.cur];
+        const uint32_t *key_in = P.scr.key[P.cur];
+        uint32_t *key_out = P.scr.key[FUSED ? 1 - P.cur : P.cur];
         const int64_t cap = P.cap;
         const double dt = P.dt;
         auto Cg = (gptr<T>)(sizeof(T) == 4 ? (const void *)P.c32 : (const void *)P.c64);
@@ -358,15 +369,15 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         }
         for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) s_cnt[q] = 0;
         if (threadIdx.x < 64) {
-            // particle runs of the block's rows and their prefix
+            // particle runs of the block's rows (in the buffer being written) and their prefix
             const int r = threadIdx.x;
             int len = 0, beg = 0;
             if (r < Sh::ROWS) {
                 const int rj = r % BY, rk = r / BY;
                 if (rj < ny && rk < nz) {
                     const int K = bi.i0 + m.n[0] * ((bi.j0 + rj) + m.n[1] * (D == 3 ? bi.k0 + rk : 0));
-                    beg = cur.cs[K];
-                    len = cur.cs[K + nx] - beg;
+                    beg = out.cs[K];
+                    len = out.cs[K + nx] - beg;
                 }
                 s_beg[r] = beg;
             }
@@ -382,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         __syncthreads();
         const int total = s_pre[Sh::ROWS];
         int st_lost = 0, st_moved = 0, st_near = 0;
-        // particle f of the block -> its row and store index
+        // particle f of the block -> its row and position in the buffer written
         auto locate_f = [&](int f, int &r) {
             r = 0;
 #pragma unroll
@@ -390,22 +401,23 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
                 if (r + step < Sh::ROWS && s_pre[r + step] <= f) r += step;
             return s_beg[r] + (f - s_pre[r]);
         };
-        // one-deep software prefetch of the next particle's state hides the
-        // HBM latency that the few resident waves cannot
-        int rn = 0, in_ = 0;
+        // one-deep software prefetch of the next particle's state
+        int rn = 0, pn = 0, sn = 0;
         int32_t Kn = 0;
         double xn_[3] = {0, 0, 0}, tn_[3] = {0, 0, 0};
-        if ((int)threadIdx.x < total) {
-            in_ = locate_f(threadIdx.x, rn);
-            Kn = cur.cell[in_];
+        auto fetch = [&](int f) {
+            pn = locate_f(f, rn);
+            sn = FUSED ? P.scr.src[pn] : pn;
+            Kn = FUSED ? (int32_t)key_in[sn] : cur.cell[sn];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                xn_[a] = cur.x[a * cap + in_];
-                tn_[a] = cur.xr[a * cap + in_];
+                xn_[a] = cur.x[a * cap + sn];
+                tn_[a] = cur.xr[a * cap + sn];
             }
-        }
+        };
+        if ((int)threadIdx.x < total) fetch(threadIdx.x);
         for (int f = threadIdx.x; f < total; f += BLOCK) {
-            const int r = rn, i = in_;
+            const int r = rn, p = pn, sidx = sn;
             const int32_t K = Kn;
             double x[3], t[3];
 #pragma unroll
@@ -413,28 +425,31 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
                 x[a] = xn_[a];
                 t[a] = tn_[a];
             }
-            if (f + BLOCK < total) {
-                in_ = locate_f(f + BLOCK, rn);
-                Kn = cur.cell[in_];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    xn_[a] = cur.x[a * cap + in_];
-                    tn_[a] = cur.xr[a * cap + in_];
-                }
-            }
+            if (f + BLOCK < total) fetch(f + BLOCK);
             bool near = false;
             const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Cg, s_w, b0, dt, x, t, (uint32_t)K, near);
-            if (key != LOST) {
+            if (key != LOST || FUSED) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    cur.x[a * cap + i] = x[a];
-                    cur.xr[a * cap + i] = t[a];
+                    out.x[a * cap + p] = x[a];
+                    out.xr[a * cap + p] = t[a];
                 }
             }
-            P.scr.key[i] = key;
+            if constexpr (FUSED) {
+                out.id[p] = cur.id[sidx];
+                out.cell[p] = K;
+                if (P.prop_f64) {
+                    for (int j = 0; j < P.n_prop; ++j)
+                        ((double *)out.prop)[j * cap + p] = ((const double *)cur.prop)[j * cap + sidx];
+                } else {
+                    for (int j = 0; j < P.n_prop; ++j)
+                        ((float *)out.prop)[j * cap + p] = ((const float *)cur.prop)[j * cap + sidx];
+                }
+            }
+            key_out[p] = key;
             const bool stay = key == (uint32_t)K;
             if (stay) {
-                // cell (i0 + ci, j0 + r % BY, k0 + r / BY) of row r
+                // column of K within row r of the block
                 const int ci = K - (bi.i0 + m.n[0] * ((bi.j0 + r % BY) + m.n[1] * (D == 3 ? bi.k0 + r / BY : 0)));
                 atomicAdd(&s_cnt[ci + BX * r], 1);
             } else if (key != LOST) {
@@ -678,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
             uint32_t key = LOST;
             int K = c0;
             if (active) {
-                key = P.scr.key[i];
+                key = P.scr.key[P.cur][i];
                 K = cur.cell[i];
             }
             const int stay = active && key == (uint32_t)K;
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
         const int64_t n = cur.cs[P.mesh.n_cells];
         const int64_t i = it.begin + threadIdx.x;
         if (i >= n || i >= it.end) continue;
-        const uint32_t key = P.scr.key[i];
+        const uint32_t key = P.scr.key[P.cur][i];
         if (key == LOST) continue;
         const int r = atomicAdd(&P.scr.cursor[key], 1);
         P.scr.src[(int64_t)nxt.cs[key] + P.scr.n_stay[key] + r] = (int32_t)i;
@@ -787,7 +802,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const ProblemDev *__restrict__
             nxt.xr[a * cap + p] = cur.xr[a * cap + s];
         }
         nxt.id[p] = cur.id[s];
-        nxt.cell[p] = (int32_t)P.scr.key[s];
+        nxt.cell[p] = (int32_t)P.scr.key[P.cur][s];
         if (P.prop_f64) {
             const double *ps = (const double *)cur.prop;
             double *pd = (double *)nxt.prop;
@@ -891,7 +906,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
         if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
         else ((float *)cur.prop)[j * cap + p] = (float)v;
     }
-    P.scr.key[p] = ok ? (uint32_t)K : LOST;
+    P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
     if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
     else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
     atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);

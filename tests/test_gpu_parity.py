@@ -189,3 +189,34 @@ def test_fp32_evaluation_against_fp64_oracle(L):
     # live sets may differ only through particles that were near the boundary
     assert abs(g["n"] - st.n) <= max(5, len(near))
     p.close()
+
+
+@pytest.mark.parametrize("dim,scheme,prec", [(3, 4, 1), (3, 2, 0), (2, 4, 0), (2, 2, 1)])
+def test_fused_steps_bit_identical_to_single_steps(L, dim, scheme, prec):
+    """advance(n) fuses each re-sort with the next advect; the result must equal n
+    separate one-step advances bit for bit (store, order, counters)."""
+    _say(f"case: fused vs single steps dim={dim} scheme={scheme} prec={prec}")
+    n = 20 if dim == 2 else 12
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    f = I.FourierField(dim, seed=900 + dim)
+    U = I.normalise_nodal(I.sample_nodes(f.velocity, I.uniform_q2_nodes(mesh)))
+    counts = np.random.default_rng(901).integers(0, 15, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=902)
+    cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=2,
+               prop_dtype=np.float32 if prec else np.float64)
+    out = []
+    for fused in (True, False):
+        p = gpu_problem(cfg)
+        if fused:
+            p.advance(0.7 / n, 9, scheme, prec)
+        else:
+            for _ in range(9):
+                p.advance(0.7 / n, 1, scheme, prec)
+        out.append((p.numpy(), p.stats()))
+        p.close()
+    (a, sa), (b, sb) = out
+    for k in ("x", "xr", "cell", "id", "prop", "cell_start"):
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("lost", "moved", "particle_steps", "steps"):
+        assert sa[k] == sb[k], k
+    assert sa["moved"] > 0
