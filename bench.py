@@ -32,14 +32,19 @@ def log(msg):
 
 
 # algorithmic bytes per particle and launch (see the design notes): d = 3,
-# 3 float properties, int32 cell/key/slot/src, uint32 id
+# 3 float properties, int32 cell/key/src, uint32 id
 def bytes_per_particle(kernel, dim=3, prop_bytes=12):
     x = 8 * dim
     return {
-        "advect": (x + x + 4) + (x + x + 4 + 4),                       # r: x, xr, cell; w: x, xr, key, slot
-        "place": 4 + 4 + 4 + 4,                                         # r: key, cell, slot; w: src
+        "advect": (x + x + 4) + (x + x + 4),                            # r: x, xr, cell; w: x, xr, key
+        "place": 4 + 4 + 4,                                             # r: key, cell; w: src
+        "fix": 0,
         "gather": (4 + 4 + x + x + 4 + prop_bytes) + (x + x + 4 + 4 + prop_bytes),
+        "gather_advect": (4 + 4 + x + x + 4 + prop_bytes) + (x + x + 4 + prop_bytes + 4 + 4),
     }[kernel]
+
+
+KERNELS = ("advect", "gather_advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip")
 
 
 def run_main(args):
@@ -91,18 +96,17 @@ def run_main(args):
     p.profile(True)
     p.advance(dt, args.steps, L.PIC_RK4, L.PIC_F32)
     kernels = {}
-    for k in ("advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip"):
+    for k in KERNELS:
         ms, n = p.profile_read(k)
         kernels[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
     p.profile(False)
     st2 = p.stats()
-    dom = max(("advect", "gather", "place"), key=lambda k: kernels[k]["total_ms"])
+    dom = max(("advect", "gather_advect", "gather", "place"), key=lambda k: kernels[k]["total_ms"])
     avg_particles = st2["particle_steps"] / max(1, st2["steps"])
-    dof_bytes = mesh.n_nodes * 16 if dom == "advect" else 0
-    bytes_launch = avg_particles * bytes_per_particle(dom) + dof_bytes
+    coeff_bytes = mesh.n_cells * 84 * 4              # per-cell monomial coefficients (f32), read once per step
+    bytes_launch = avg_particles * bytes_per_particle(dom) + (coeff_bytes if "advect" in dom else 0)
     achieved = bytes_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-    step_bytes = avg_particles * (bytes_per_particle("advect") + bytes_per_particle("place") +
-                                  bytes_per_particle("gather")) + mesh.n_nodes * 16
+    step_bytes = avg_particles * (bytes_per_particle("gather_advect") + bytes_per_particle("place")) + coeff_bytes
     step_ms = 1e3 * elapsed / args.steps
     line = {
         "metric": "particle-steps/s (advect+locate+sort)",
