@@ -16,6 +16,238 @@
 
 namespace pic {
 
+// ---------------------------------------------------------------------------
+// uniform meshes: blocks of cells of the step's input state, dU pre-reduced
+// in an LDS window of the block's Q2 nodes plus a one-cell halo
+// ---------------------------------------------------------------------------
+template <int D, int BX, int BY, int BZ> struct NodeWin {
+    static constexpr int WX = 2 * BX + 5;
+    static constexpr int WY = 2 * BY + 5;
+    static constexpr int WZ = D == 3 ? 2 * BZ + 5 : 1;
+    static constexpr int NODES = WX * WY * WZ;
+    static constexpr int ROWS = BY * (D == 3 ? BZ : 1);
+};
+
+// reference gradient Gr[c][r] = d u_c / d t_r of the nodal field at (ijk, t) and
+// the nodal basis values phi[27] (3D) / [9] (2D)
+template <int D>
+__device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, double>::type> U, int nnx, int nny,
+                                                   const int ijk[3], const double *t, double Gr[3][3], double *phi)
+{
+    double l[3][3], dl[3][3];
+    for (int a = 0; a < D; ++a) {
+        lag3(t[a], l[a]);
+        dlag3(t[a], dl[a]);
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) Gr[c][r] = 0.0;
+    const int64_t sz = (int64_t)nnx * nny;
+    const int64_t base = 2 * ijk[0] + (int64_t)nnx * (2 * ijk[1]) + (D == 3 ? sz * (2 * ijk[2]) : 0);
+#pragma unroll
+    for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const auto v = U[base + a + (int64_t)nnx * b + sz * c3];
+                double w0, w1, w2 = 0.0, ph;
+                if constexpr (D == 2) {
+                    w0 = dl[0][a] * l[1][b];
+                    w1 = l[0][a] * dl[1][b];
+                    ph = l[0][a] * l[1][b];
+                } else {
+                    w0 = dl[0][a] * l[1][b] * l[2][c3];
+                    w1 = l[0][a] * dl[1][b] * l[2][c3];
+                    w2 = l[0][a] * l[1][b] * dl[2][c3];
+                    ph = l[0][a] * l[1][b] * l[2][c3];
+                }
+                phi[a + 3 * b + 9 * c3] = ph;
+                const double vc[3] = {(double)nv_x(v), (double)nv_y(v), (double)nv_z(v)};
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    Gr[c][0] = fma(vc[c], w0, Gr[c][0]);
+                    Gr[c][1] = fma(vc[c], w1, Gr[c][1]);
+                    if constexpr (D == 3) Gr[c][2] = fma(vc[c], w2, Gr[c][2]);
+                }
+            }
+}
+
+/*
+ * One reverse step on a uniform mesh.  Work item = block of cells of the
+ * step's input state (its particles are runs of consecutive cells); dst[i] is
+ * the output position of input particle i (-1 if it was lost).  Stage points
+ * are recomputed with the forward's own location and evaluation, the reverse
+ * sweep is applied, lam_out[i] is written, and the dU contributions of the
+ * block are summed in LDS before one atomic per window node.
+ */
+template <int D, int S, int BX, int BY, int BZ>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restrict__ probs,
+                                                       const BlockItem *__restrict__ work, int n_work,
+                                                       const double *__restrict__ x_in, const double *__restrict__ xr_in,
+                                                       const int32_t *__restrict__ cell_in, const int32_t *__restrict__ cs_in,
+                                                       const int32_t *__restrict__ dst, const double *__restrict__ lam_next,
+                                                       double *__restrict__ lam_out, double *__restrict__ dU)
+{
+    using Wn = NodeWin<D, BX, BY, BZ>;
+    using V = typename NodeVec<D, double>::type;
+    __shared__ double s_acc[Wn::NODES * D];
+    __shared__ int s_pre[Wn::ROWS + 1];
+    __shared__ int s_beg[Wn::ROWS];
+    const ProblemDev &P = probs[0];
+    const MeshDev &m = P.mesh;
+    const int64_t cap = P.cap;
+    const double dt = P.dt;
+    auto Cg = (gptr<double>)(const void *)P.c64;
+    auto Ug = (gptr<V>)P.u64;
+    const int64_t nn = m.n_nodes;
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const BlockItem bi = work[w];
+        const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
+        const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
+        const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
+        for (int q = threadIdx.x; q < Wn::NODES * D; q += BLOCK) s_acc[q] = 0.0;
+        if (threadIdx.x < 64) {
+            const int r = threadIdx.x;
+            int len = 0, beg = 0;
+            if (r < Wn::ROWS) {
+                const int rj = r % BY, rk = r / BY;
+                if (rj < ny && rk < nz) {
+                    const int K = bi.i0 + m.n[0] * ((bi.j0 + rj) + m.n[1] * (D == 3 ? bi.k0 + rk : 0));
+                    beg = cs_in[K];
+                    len = cs_in[K + nx] - beg;
+                }
+                s_beg[r] = beg;
+            }
+            int inc = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(inc, o, 64);
+                if (r >= o) inc += v;
+            }
+            if (r < Wn::ROWS) s_pre[r + 1] = inc;
+            if (r == 0) s_pre[0] = 0;
+        }
+        __syncthreads();
+        const int total = s_pre[Wn::ROWS];
+        for (int f = threadIdx.x; f < total; f += BLOCK) {
+            int r = 0;
+#pragma unroll
+            for (int step = Wn::ROWS / 2; step >= 1; step >>= 1)
+                if (r + step < Wn::ROWS && s_pre[r + step] <= f) r += step;
+            const int i = s_beg[r] + (f - s_pre[r]);
+            const int p = dst[i];
+            if (p < 0) {
+                for (int a = 0; a < D; ++a) lam_out[a * cap + i] = 0.0;
+                continue;
+            }
+            double x[3], ty[4][3], k[4][3], u[3], y[3];
+            int jk[4][3];
+            bool near = false;
+            for (int a = 0; a < D; ++a) {
+                x[a] = x_in[a * cap + i];
+                ty[0][a] = xr_in[a * cap + i];
+            }
+            ijk_of<D>(m, (uint32_t)cell_in[i], jk[0]);
+            constexpr int NS = S == 4 ? 4 : S;
+            for (int st = 0; st < NS; ++st) {
+                if (st > 0) {
+                    const double fct = (S == 4 && st == 3) ? 1.0 : 0.5;
+                    for (int a = 0; a < D; ++a) y[a] = x[a] + fct * k[st - 1][a];
+                    locate_stage<D>(m, y, jk[st], ty[st], near);
+                }
+                const int64_t K = cell_of<D>(m, jk[st]);
+                eval_mono<D, double>(Cg + K * Mono<D>::STRIDE, ty[st], u);
+                for (int a = 0; a < D; ++a) k[st][a] = dt * u[a];
+            }
+            double lam[3], kb[4][3], yb[4][3];
+            for (int a = 0; a < D; ++a) lam[a] = lam_next[a * cap + p];
+            for (int a = 0; a < D; ++a) {
+                if constexpr (S == 1) {
+                    kb[0][a] = lam[a];
+                } else if constexpr (S == 2) {
+                    kb[1][a] = lam[a];
+                    kb[0][a] = 0.0;
+                } else {
+                    kb[0][a] = lam[a] / 6.0;
+                    kb[1][a] = lam[a] / 3.0;
+                    kb[2][a] = lam[a] / 3.0;
+                    kb[3][a] = lam[a] / 6.0;
+                }
+            }
+            for (int st = NS - 1; st >= 0; --st) {
+                double Gr[3][3], phi[27];
+                grad_basis_uniform<D>(Ug, m.nnx, m.nny, jk[st], ty[st], Gr, phi);
+                for (int j = 0; j < D; ++j) {
+                    double acc = 0.0;
+                    for (int c = 0; c < D; ++c) acc += Gr[c][j] * kb[st][c];
+                    yb[st][j] = dt * acc / m.h[j];
+                }
+                // dU_c[node] += dt phi_node kb_c : LDS window if the cell's nodes are in it
+                const int di = jk[st][0] - b0[0] + 1, dj = jk[st][1] - b0[1] + 1, dk = jk[st][2] - b0[2] + 1;
+                bool inw = ((unsigned)di < (unsigned)(BX + 2)) & ((unsigned)dj < (unsigned)(BY + 2));
+                if constexpr (D == 3) inw &= (unsigned)dk < (unsigned)(BZ + 2);
+                for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
+                    for (int b = 0; b < 3; ++b)
+                        for (int a = 0; a < 3; ++a) {
+                            const double f = dt * phi[a + 3 * b + 9 * c3];
+                            if (inw) {
+                                const int q = (2 * di + a) + Wn::WX * ((2 * dj + b) + Wn::WY * (D == 3 ? 2 * dk + c3 : 0));
+                                for (int c = 0; c < D; ++c) atomicAdd(&s_acc[c * Wn::NODES + q], f * kb[st][c]);
+                            } else {
+                                const int64_t g = (2 * jk[st][0] + a) + (int64_t)m.nnx * ((2 * jk[st][1] + b) +
+                                                  (int64_t)m.nny * (D == 3 ? 2 * jk[st][2] + c3 : 0));
+                                for (int c = 0; c < D; ++c) unsafeAtomicAdd(&dU[c * nn + g], f * kb[st][c]);
+                            }
+                        }
+                if constexpr (S == 2) {
+                    if (st == 1)
+                        for (int a = 0; a < D; ++a) kb[0][a] = 0.5 * yb[1][a];
+                } else if constexpr (S == 4) {
+                    if (st == 3)
+                        for (int a = 0; a < D; ++a) kb[2][a] += yb[3][a];
+                    if (st == 2)
+                        for (int a = 0; a < D; ++a) kb[1][a] += 0.5 * yb[2][a];
+                    if (st == 1)
+                        for (int a = 0; a < D; ++a) kb[0][a] += 0.5 * yb[1][a];
+                }
+            }
+            for (int a = 0; a < D; ++a) {
+                double v = lam[a];
+                for (int st = 0; st < NS; ++st) v += yb[st][a];
+                lam_out[a * cap + i] = v;
+            }
+        }
+        __syncthreads();
+        // flush the window: window node (wx, wy, wz) = global node 2*b0 - 2 + w
+        for (int q = threadIdx.x; q < Wn::NODES; q += BLOCK) {
+            const int wx = q % Wn::WX, wy = (q / Wn::WX) % Wn::WY, wz = q / (Wn::WX * Wn::WY);
+            const int gx = 2 * b0[0] - 2 + wx, gy = 2 * b0[1] - 2 + wy, gz = D == 3 ? 2 * b0[2] - 2 + wz : 0;
+            if (gx < 0 || gx > 2 * m.n[0] || gy < 0 || gy > 2 * m.n[1] || gz < 0 || gz > (D == 3 ? 2 * m.n[2] : 0))
+                continue;
+            const int64_t g = gx + (int64_t)m.nnx * (gy + (int64_t)m.nny * gz);
+            for (int c = 0; c < D; ++c) {
+                const double v = s_acc[c * Wn::NODES + q];
+                if (v != 0.0) unsafeAtomicAdd(&dU[c * nn + g], v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// dst[i] = output position of input particle i (or -1): inverse of src
+__global__ void k_invert(const int32_t *__restrict__ src, const int32_t *__restrict__ cs_in,
+                         const int32_t *__restrict__ cs_out, int64_t nc, int32_t *__restrict__ dst, int64_t cap)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < cap && q < cs_in[nc]) dst[q] = -1;
+}
+__global__ void k_invert_scatter(const int32_t *__restrict__ src, const int32_t *__restrict__ cs_out, int64_t nc,
+                                 int32_t *__restrict__ dst, int64_t cap)
+{
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p < cap && p < cs_out[nc]) dst[src[p]] = (int32_t)p;
+}
+
 // physical gradient G[c][j] = d u_c / d x_j at (K, t)
 template <int D, int KIND>
 __device__ __forceinline__ void grad_phys(const MeshDev &m, const typename NodeVec<D, double>::type *U, int64_t K,

@@ -212,7 +212,7 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
     char *cur = take(4 * (size_t)(nc + 1));
     char *chk = take(8 * (size_t)(n_chunks(nc) + 1));
     char *st = take(8 * (size_t)ST_COUNT * STAT_STRIPES);
-    char *nid = take(8);
+    char *nid = take(8 * (size_t)(1 + STAT_STRIPES));
     char *fl = take(16);
     if (s) {
         s->key[0] = (uint32_t *)key0;
@@ -831,9 +831,10 @@ extern "C" pic_status pic_seed_reference(pic_ctx *c, const int32_t *counts, cons
     int32_t cur = 0;
     if ((s = pic_current_buffer(c, &cur))) return s;
     HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur], cs.data(), sizeof(int32_t) * cs.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8 * (1 + STAT_STRIPES), c->stream));
     s = c->mesh.dim == 2 ? seed_ref_launch<2>(c, xr, ids, n, prop_init, prop_in) : seed_ref_launch<3>(c, xr, ids, n, prop_init, prop_in);
     if (s) return s;
+    LAUNCH(c, "seed", k_reduce_next_id, 1u, (unsigned)STAT_STRIPES, (const ProblemDev *)c->d_prob);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
@@ -854,11 +855,12 @@ extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint
     HIPCHK(c, hipMemsetAsync(c->scr.n_stay, 0, sizeof(int32_t) * nc, c->stream));
     HIPCHK(c, hipMemsetAsync(c->scr.n_arrive, 0, sizeof(int32_t) * nc, c->stream));
     HIPCHK(c, hipMemsetAsync(c->scr.cursor, 0, sizeof(int32_t) * (nc + 1), c->stream));
-    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8 * (1 + STAT_STRIPES), c->stream));
     int32_t n32 = (int32_t)n;
     HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur] + nc, &n32, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     s = c->mesh.dim == 2 ? seed_pos_launch<2>(c, x, ids, n, prop_init, prop_in) : seed_pos_launch<3>(c, x, ids, n, prop_init, prop_in);
     if (s) return s;
+    LAUNCH(c, "seed_positions", k_reduce_next_id, 1u, (unsigned)STAT_STRIPES, (const ProblemDev *)c->d_prob);
     s = enqueue_sort(c, c->d_prob, 0, true);
     if (s) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));

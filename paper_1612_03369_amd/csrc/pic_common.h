@@ -72,7 +72,7 @@ struct ScratchDev {
     int32_t *cursor;      // [nc]
     int64_t *chunk;       // [n_chunks + 1]
     unsigned long long *stats;  // [STAT_STRIPES][ST_COUNT]
-    unsigned long long *next_id;// [1]
+    unsigned long long *next_id;// [1 + STAT_STRIPES]: next_id[0], then striped maxima written by seeding
     int32_t *flags;       // [4]
 };
 

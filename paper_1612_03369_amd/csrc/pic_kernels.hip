@@ -862,7 +862,21 @@ __global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int
         }
         idmax = idmax > (unsigned long long)ids[p] + 1ull ? idmax : (unsigned long long)ids[p] + 1ull;
     }
-    if (idmax) atomicMax(P.scr.next_id, idmax);
+    if (idmax) atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], idmax);
+}
+
+// next_id = max over the striped maxima (one workgroup of STAT_STRIPES threads)
+__global__ void k_reduce_next_id(const ProblemDev *probs)
+{
+    __shared__ unsigned long long s_m[STAT_STRIPES];
+    const ProblemDev &P = probs[0];
+    s_m[threadIdx.x] = P.scr.next_id[1 + threadIdx.x];
+    __syncthreads();
+    for (int o = STAT_STRIPES / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s_m[threadIdx.x] = s_m[threadIdx.x] > s_m[threadIdx.x + o] ? s_m[threadIdx.x] : s_m[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.scr.next_id[0] = s_m[0] > P.scr.next_id[0] ? s_m[0] : P.scr.next_id[0];
 }
 
 // Prescribed locations: locate each point with the global search and write it
@@ -909,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
     P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
     if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
     else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
-    atomicMax(P.scr.next_id, (unsigned long long)ids[p] + 1ull);
+    atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], (unsigned long long)ids[p] + 1ull);
 }
 
 // ===========================================================================
