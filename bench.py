@@ -103,10 +103,11 @@ def run_main(args):
     st2 = p.stats()
     dom = max(("advect", "gather_advect", "gather", "place"), key=lambda k: kernels[k]["total_ms"])
     avg_particles = st2["particle_steps"] / max(1, st2["steps"])
-    coeff_bytes = mesh.n_cells * 84 * 4              # per-cell monomial coefficients (f32), read once per step
-    bytes_launch = avg_particles * bytes_per_particle(dom) + (coeff_bytes if "advect" in dom else 0)
+    n_nodes = int(np.prod(mesh.node_shape))
+    field_bytes = n_nodes * 3 * 4                     # Q2 nodal field (3 f32 components), read once per step
+    bytes_launch = avg_particles * bytes_per_particle(dom) + (field_bytes if "advect" in dom else 0)
     achieved = bytes_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-    step_bytes = avg_particles * (bytes_per_particle("gather_advect") + bytes_per_particle("place")) + coeff_bytes
+    step_bytes = avg_particles * (bytes_per_particle("gather_advect") + bytes_per_particle("place")) + field_bytes
     step_ms = 1e3 * elapsed / args.steps
     line = {
         "metric": "particle-steps/s (advect+locate+sort)",

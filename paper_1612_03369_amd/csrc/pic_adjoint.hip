@@ -97,7 +97,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
     const MeshDev &m = P.mesh;
     const int64_t cap = P.cap;
     const double dt = P.dt;
-    auto Cg = (gptr<double>)(const void *)P.c64;
     auto Ug = (gptr<V>)P.u64;
     const int64_t nn = m.n_nodes;
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
@@ -155,8 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
                     for (int a = 0; a < D; ++a) y[a] = x[a] + fct * k[st - 1][a];
                     locate_stage<D>(m, y, jk[st], ty[st], near);
                 }
-                const int64_t K = cell_of<D>(m, jk[st]);
-                eval_mono<D, double>(Cg + K * Mono<D>::STRIDE, ty[st], u);
+                eval_q2_ijk<D, double>(Ug, m.nnx, m.nny, jk[st], ty[st], u);
                 for (int a = 0; a < D; ++a) k[st][a] = dt * u[a];
             }
             double lam[3], kb[4][3], yb[4][3];

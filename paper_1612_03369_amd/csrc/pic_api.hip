@@ -44,8 +44,6 @@ struct pic_ctx {
     std::vector<int32_t> h_anchor;
     // field
     void *u64 = nullptr, *u32 = nullptr;
-    double *c64 = nullptr;            // uniform meshes: monomial coefficients per cell
-    float *c32 = nullptr;
     bool have_field = false;
     // store
     bool bound = false;
@@ -179,11 +177,7 @@ void free_mesh(pic_ctx *c)
     c->mesh_allocs.clear();
     if (c->u64) hipFree(c->u64);
     if (c->u32) hipFree(c->u32);
-    if (c->c64) hipFree(c->c64);
-    if (c->c32) hipFree(c->c32);
     c->u64 = c->u32 = nullptr;
-    c->c64 = nullptr;
-    c->c32 = nullptr;
     c->have_mesh = false;
     c->node_xyz.clear();
     c->node_hanging.clear();
@@ -260,7 +254,7 @@ pic_status upload_problem(pic_ctx *c)
 #define PIC_BLK3_F32 4, 4, 4
 #endif
 constexpr int BLK3_F32[3] = {PIC_BLK3_F32};
-constexpr int BLK3_F64[3] = {4, 2, 2};
+constexpr int BLK3_F64[3] = {4, 4, 4};
 constexpr int BLK2[3] = {8, 8, 1};
 inline const int *block_shape(int dim, int prec)
 {
@@ -436,13 +430,13 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
     const int pr = prec == PIC_F32;
     BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false);
     BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true);
-    LAUNCH(c, "advect", fa, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+    LAUNCH(c, "advect", fa, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0);
         if (s) return s;
         LAUNCH(c, "place", k_place, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
         LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
-        LAUNCH(c, "gather_advect", ff, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+        LAUNCH(c, "gather_advect", ff, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
         LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, 1);
     }
     return enqueue_sort(c, dp, 1);
@@ -453,7 +447,7 @@ pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
     if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
         BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false);
         const int pr = prec == PIC_F32;
-        LAUNCH(c, "advect", f, (unsigned)c->n_blk[pr], BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
+        LAUNCH(c, "advect", f, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
                c->n_blk[pr]);
         return enqueue_sort(c, dp, 1);
     }
@@ -536,10 +530,11 @@ extern "C" pic_status pic_mesh_uniform(pic_ctx *c, int dim, const int32_t n[3], 
     }
     m.nnx = 2 * m.n[0] + 1;
     m.nny = 2 * m.n[1] + 1;
+    m.nnz = dim == 3 ? 2 * m.n[2] + 1 : 1;
     m.nvx = m.n[0] + 1;
     m.nvy = m.n[1] + 1;
     m.n_cells = nc;
-    m.n_nodes = (int64_t)m.nnx * m.nny * (dim == 3 ? 2 * m.n[2] + 1 : 1);
+    m.n_nodes = (int64_t)m.nnx * m.nny * m.nnz;
     m.n_vert = (int64_t)m.nvx * m.nvy * (dim == 3 ? m.n[2] + 1 : 1);
     mesh_common(m);
     c->mesh = m;
@@ -669,26 +664,9 @@ extern "C" pic_status pic_set_velocity(pic_ctx *c, const void *U, int prec)
         s = resolve_hanging(c);
         if (s) return s;
     }
-    if (c->mesh.kind == MESH_UNIFORM) {
-        const int stride = d == 3 ? Mono<3>::STRIDE : Mono<2>::STRIDE;
-        const size_t nco = (size_t)stride * (size_t)c->mesh.n_cells;
-        if (!c->c64) {
-            if ((s = dalloc(c, &c->c64, nco))) return s;
-            if ((s = dalloc(c, &c->c32, nco))) return s;
-        }
-        unsigned gc = (unsigned)((c->mesh.n_cells + BLOCK - 1) / BLOCK);
-        if (d == 3)
-            hipLaunchKernelGGL(k_mono_coeffs<3>, dim3(gc), dim3(BLOCK), 0, c->stream, c->mesh, (const void *)c->u64, c->c64, c->c32);
-        else
-            hipLaunchKernelGGL(k_mono_coeffs<2>, dim3(gc), dim3(BLOCK), 0, c->stream, c->mesh, (const void *)c->u64, c->c64, c->c32);
-        HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
     c->have_field = true;
     c->h_prob.u64 = c->u64;
     c->h_prob.u32 = c->u32;
-    c->h_prob.c64 = c->c64;
-    c->h_prob.c32 = c->c32;
     if (c->bound) return upload_problem(c);
     return PIC_OK;
 }
@@ -731,8 +709,6 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     P.dt = 0.0;
     P.u64 = c->u64;
     P.u32 = c->u32;
-    P.c64 = c->c64;
-    P.c32 = c->c32;
     P.scr = c->scr;
     c->last_dt = 0.0;
     // zeroed state: empty buffers, zero counters

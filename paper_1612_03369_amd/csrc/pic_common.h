@@ -35,7 +35,7 @@ constexpr int STAT_STRIPES = 256;
 struct MeshDev {
     int dim, kind;
     int n[3];                 // structured: cells per axis
-    int nnx, nny;             // structured Q2 node grid extents 2n+1
+    int nnx, nny, nnz;        // structured Q2 node grid extents 2n+1 (nnz = 1 in 2D)
     int nvx, nvy;             // structured vertex grid extents n+1
     int64_t n_cells, n_nodes, n_vert;
     double lo[3], hi[3], h[3], inv_h[3];
@@ -302,20 +302,22 @@ __device__ __forceinline__ bool locate_uniform(const MeshDev &m, const double *y
     return inside;
 }
 
-// Q2 evaluation on a structured node grid from (i,j,k), sum-factorised.
-template <int D, typename T>
-__device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U, int nnx, int nny, const int ijk[3],
-                                            const double *tr, double *u)
+// Q2 evaluation on a structured node grid, sum-factorised.  base = index of
+// local node (0,0,0) of the cell, sy / sz = index strides of the grid's y and
+// z rows.  The grid may be the global node array or a window of it in LDS:
+// the arithmetic, and hence the rounding, is the same for both.
+template <int D, typename T, typename Ptr, typename I>
+__device__ __forceinline__ void eval_q2_at(Ptr U, I base, I sy, I sz, const double *tr, double *u)
 {
     T la[3], lb[3];
     lag3((T)tr[0], la);
     lag3((T)tr[1], lb);
     if constexpr (D == 2) {
-        const int base = 2 * ijk[0] + nnx * (2 * ijk[1]);
+        const I nnx = sy;
         T a0 = 0, a1 = 0;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const int r = base + nnx * b;
+            const I r = base + nnx * b;
             const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
             a0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), a0);
             a1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), a1);
@@ -325,15 +327,14 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
     } else {
         T lc[3];
         lag3((T)tr[2], lc);
-        const int sz = nnx * nny;
-        const int base = 2 * ijk[0] + nnx * (2 * ijk[1]) + sz * (2 * ijk[2]);
+        const I nnx = sy;
         T a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
+#pragma unroll PIC_EVAL_UNROLL
         for (int c = 0; c < 3; ++c) {
             T r0 = 0, r1 = 0, r2 = 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const int r = base + nnx * b + sz * c;
+                const I r = base + nnx * b + sz * c;
                 const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
                 r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
                 r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
@@ -349,53 +350,14 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
     }
 }
 
-// ---------------------------------------------------------------------------
-// monomial (power) form of the Q2 field per cell: on the reference cell
-//   u_c(t) = sum_{a,b,c} C[comp][c][b][a] t0^a t1^b t2^c,
-// obtained from the nodal values by the 1D change of basis
-//   (U0, U1, U2) -> (U0, -3 U0 + 4 U1 - U2, 2 U0 - 4 U1 + 2 U2)
-// along each axis; evaluated by nested Horner steps (26 FMA per component
-// in 3D).  Cells are stored with a padded stride (84 values in 3D, 20 in 2D)
-// that keeps 16-byte alignment and spreads neighbouring cells over the LDS
-// banks.
-// ---------------------------------------------------------------------------
-template <int D> struct Mono {
-    static constexpr int NCOEF = D == 3 ? 27 : 9;
-    static constexpr int STRIDE = D == 3 ? 84 : 20;
-};
-
-template <int D, typename T, typename Ptr>
-__device__ __forceinline__ void eval_mono(Ptr C, const double *tr, double *u)
+// The same on the global node array of a structured mesh, cell (i,j,k).
+template <int D, typename T>
+__device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U, int nnx, int nny, const int ijk[3],
+                                            const double *tr, double *u)
 {
-    const T t0 = (T)tr[0], t1 = (T)tr[1];
-    if constexpr (D == 2) {
-#pragma unroll
-        for (int comp = 0; comp < 2; ++comp) {
-            const auto *c = C + comp * 9;
-            T r[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) r[b] = fma_t(t0, fma_t(t0, (T)c[3 * b + 2], (T)c[3 * b + 1]), (T)c[3 * b]);
-            u[comp] = (double)fma_t(t1, fma_t(t1, r[2], r[1]), r[0]);
-        }
-    } else {
-        const T t2 = (T)tr[2];
-#pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-            const auto *c = C + comp * 27;
-            T pl[3];
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                T r[3];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const int o = 9 * cc + 3 * b;
-                    r[b] = fma_t(t0, fma_t(t0, (T)c[o + 2], (T)c[o + 1]), (T)c[o]);
-                }
-                pl[cc] = fma_t(t1, fma_t(t1, r[2], r[1]), r[0]);
-            }
-            u[comp] = (double)fma_t(t2, fma_t(t2, pl[2], pl[1]), pl[0]);
-        }
-    }
+    const int64_t sz = (int64_t)nnx * nny;
+    const int64_t base = 2 * ijk[0] + (int64_t)nnx * (2 * ijk[1]) + (D == 3 ? sz * (2 * ijk[2]) : 0);
+    eval_q2_at<D, T>(U, base, (int64_t)nnx, sz, tr, u);
 }
 
 // Stage-point location on a uniform mesh: cell and reference coordinates from

@@ -17,8 +17,6 @@ struct ProblemDev {
     double dt;
     const void *u64;         // repacked field, double
     const void *u32;         // repacked field, float
-    const double *c64;       // uniform meshes: per-cell monomial coefficients, double
-    const float *c32;        // ... and float
     ScratchDev scr;
     // adjoint: arrays of the segment being replayed
     const double *adj_lam_in;  // [dim][cap] lambda of the next step, in that step's order

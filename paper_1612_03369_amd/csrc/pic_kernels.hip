@@ -229,21 +229,29 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
 // advect + locate on uniform meshes with the field of a block of cells staged
 // in LDS
 // ===========================================================================
-// Block of BX x BY x BZ cells; the LDS window holds the monomial coefficients
-// of the block's cells plus a one-cell halo, (BX+2) x (BY+2) x (BZ+2) cells.
+// Block of BX x BY x BZ cells; the LDS window holds the Q2 nodes of the
+// block's cells plus a one-cell halo: (2(BX+2)+1) x (2(BY+2)+1) x (2(BZ+2)+1)
+// nodes, node (wx, wy, wz) = global node (2(i0-1)+wx, 2(j0-1)+wy, 2(k0-1)+wz).
+// Neighbouring cells share their face nodes, so the window holds about 8
+// nodes per cell instead of the 27 a per-cell layout would need.
 template <int D, int BX, int BY, int BZ> struct BlockShape {
     static constexpr int CX = BX + 2;
     static constexpr int CY = BY + 2;
     static constexpr int CZ = D == 3 ? BZ + 2 : 1;
-    static constexpr int WCELLS = CX * CY * CZ;
+    static constexpr int WX = 2 * CX + 1;
+    static constexpr int WY = 2 * CY + 1;
+    static constexpr int WZ = D == 3 ? 2 * CZ + 1 : 1;
+    static constexpr int NODES = WX * WY * WZ;
     static constexpr int CELLS = BX * BY * (D == 3 ? BZ : 1);
     static constexpr int ROWS = BY * (D == 3 ? BZ : 1);
 };
 
 // Field at the reference point t of cell ijk: from the LDS window when the
-// cell lies in the block or its halo, else from the global coefficient array.
+// cell lies in the block or its halo, else from the global node array (same
+// arithmetic, same rounding).
 template <int D, typename T, int BX, int BY, int BZ>
-__device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<T> Cg, const T *W, const int *b0, const int ijk[3],
+__device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> Ug,
+                                         const typename NodeVec<D, T>::type *W, const int *b0, const int ijk[3],
                                          const double *t, double *u)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
@@ -251,57 +259,64 @@ __device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<T> Cg, const T *
     bool in = ((unsigned)di < (unsigned)Sh::CX) & ((unsigned)dj < (unsigned)Sh::CY);
     if constexpr (D == 3) in &= (unsigned)dk < (unsigned)Sh::CZ;
     if (in) {
-        eval_mono<D, T>(W + (di + Sh::CX * (dj + Sh::CY * (D == 3 ? dk : 0))) * Mono<D>::STRIDE, t, u);
+        const int base = 2 * di + Sh::WX * (2 * dj + (D == 3 ? Sh::WY * 2 * dk : 0));
+        eval_q2_at<D, T>(W, base, (int)Sh::WX, (int)(Sh::WX * Sh::WY), t, u);
     } else {
-        const int64_t K = cell_of<D>(m, ijk);
-        eval_mono<D, T>(Cg + K * Mono<D>::STRIDE, t, u);
+        eval_q2_ijk<D, T>(Ug, m.nnx, m.nny, ijk, t, u);
     }
 }
 
 template <int D, int S, typename T, int BX, int BY, int BZ>
-__device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<T> Cg, const T *W, const int *b0, double dt,
+__device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> Ug,
+                                                   const typename NodeVec<D, T>::type *W, const int *b0, double dt,
                                                    double *x, double *t, uint32_t K, bool &near)
 {
     int ijk[3], jk[3];
-    double u[3], k1[3], y[3], ty[3], xn[3];
+    double u[3], y[3], ty[3], xn[3];
     ijk_of<D>(m, K, ijk);
-    eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, ijk, t, u);
-#pragma unroll
-    for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
+    eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, ijk, t, u);
     bool in = true;
     if constexpr (S == 1) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a];
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
     } else if constexpr (S == 2) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
+        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * (dt * u[a]);
         in &= locate_stage<D>(m, y, jk, ty, near);
-        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
+        eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
     } else {
-        double k2[3], k3[3];
-#pragma unroll
-        for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
-        in &= locate_stage<D>(m, y, jk, ty, near);
-        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            k2[a] = dt * u[a];
-            y[a] = x[a] + 0.5 * k2[a];
-        }
-        in &= locate_stage<D>(m, y, jk, ty, near);
-        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            k3[a] = dt * u[a];
-            y[a] = x[a] + k3[a];
-        }
-        in &= locate_stage<D>(m, y, jk, ty, near);
-        eval_blk<D, T, BX, BY, BZ>(m, Cg, W, b0, jk, ty, u);
+        // xn accumulates x + k1/6 + k2/3 + k3/3 + k4/6 left to right as each
+        // stage slope becomes known, so no slope is kept beyond its stage
         const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+        double k[3];
 #pragma unroll
-        for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
+        for (int a = 0; a < D; ++a) {
+            k[a] = dt * u[a];
+            xn[a] = x[a] + k[a] * s6;
+            y[a] = x[a] + 0.5 * k[a];
+        }
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k[a] = dt * u[a];
+            xn[a] = xn[a] + k[a] * s3;
+            y[a] = x[a] + 0.5 * k[a];
+        }
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            k[a] = dt * u[a];
+            xn[a] = xn[a] + k[a] * s3;
+            y[a] = x[a] + k[a];
+        }
+        in &= locate_stage<D>(m, y, jk, ty, near);
+        eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = xn[a] + (dt * u[a]) * s6;
     }
     near |= near_boundary<D>(m, xn);
     double tn[3];
@@ -318,8 +333,7 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<T> Cg,
 
 /*
  * Work item = block of cells of a uniform mesh.  The workgroup copies the
- * monomial coefficients of the block's cells plus a one-cell halo into LDS
- * once, then advances every particle of the block's cells; stage points in
+ * Q2 nodes of the block's cells plus a one-cell halo into LDS once, then advances every particle of the block's cells; stage points in
  * the halo read LDS, the rare ones farther away read global memory.
  *
  * FUSED = false: the particles are those of the current buffer; new location,
@@ -331,14 +345,29 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<T> Cg,
  * buffer.  A fused step is thus "finish the previous step's permutation and
  * compute the next step's keys" in one pass over the particle state.
  */
+#ifndef PIC_ADV_THREADS
+#define PIC_ADV_THREADS 256         // threads per workgroup of the block kernels
+#endif
+#ifndef PIC_BLK_MIN_WAVES
+#define PIC_BLK_MIN_WAVES 3         // 3D single-precision kernels: cap registers for this many waves per SIMD
+#endif
+// Register cap of the block kernels, as waves per SIMD (1 = compiler's choice).
+// The 3D single-precision kernels run at three waves with no spills; the
+// double-precision ones would spill under that cap and get two.
+template <int D, typename T> struct BlkWaves {
+    static constexpr int value = D == 2 ? 1 : (sizeof(T) == 4 ? (PIC_BLK_MIN_WAVES > 0 ? PIC_BLK_MIN_WAVES : 1) : 2);
+};
+#ifndef PIC_BLK_PREFETCH
+#define PIC_BLK_PREFETCH 1          // 1: load the next particle's state while advancing this one
+#endif
+constexpr int ADV_BLOCK = PIC_ADV_THREADS;
 template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED>
-__global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const ProblemDev *__restrict__ probs,
+__global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
                                                                       const BlockItem *__restrict__ work, int n_work)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
-    constexpr int STRIDE = Mono<D>::STRIDE;
-    constexpr int CHUNKS = STRIDE * (int)sizeof(T) / 16;       // 16-byte pieces per cell
-    __shared__ __attribute__((aligned(16))) T s_w[Sh::WCELLS * STRIDE];
+    using V = typename NodeVec<D, T>::type;
+    __shared__ V s_w[Sh::NODES];
     __shared__ int s_cnt[Sh::CELLS];
     __shared__ int s_pre[Sh::ROWS + 1];
     __shared__ int s_beg[Sh::ROWS];
@@ -352,22 +381,19 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         uint32_t *key_out = P.scr.key[FUSED ? 1 - P.cur : P.cur];
         const int64_t cap = P.cap;
         const double dt = P.dt;
-        auto Cg = (gptr<T>)(sizeof(T) == 4 ? (const void *)P.c32 : (const void *)P.c64);
+        auto Ug = (gptr<V>)(sizeof(T) == 4 ? P.u32 : P.u64);
         const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
         const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
         const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
-        // stage the window: window cell (wx, wy, wz) = mesh cell b0 - 1 + w
-        for (int q = threadIdx.x; q < Sh::WCELLS * CHUNKS; q += BLOCK) {
-            const int wc = q / CHUNKS, ch = q - wc * CHUNKS;
-            const int wx = wc % Sh::CX, wy = (wc / Sh::CX) % Sh::CY, wz = wc / (Sh::CX * Sh::CY);
-            const int ci = bi.i0 - 1 + wx, cj = bi.j0 - 1 + wy, ck = D == 3 ? bi.k0 - 1 + wz : 0;
-            if (ci >= 0 && ci < m.n[0] && cj >= 0 && cj < m.n[1] && ck >= 0 && ck < (D == 3 ? m.n[2] : 1)) {
-                const int64_t K = ci + (int64_t)m.n[0] * (cj + (int64_t)m.n[1] * ck);
-                const float4 v = ((gptr<float4>)(Cg + K * STRIDE))[ch];
-                reinterpret_cast<float4 *>(s_w + wc * STRIDE)[ch] = v;
-            }
+        // stage the window; nodes beyond the mesh are never read (stage
+        // points are clamped to mesh cells) and are left unset
+        for (int q = threadIdx.x; q < Sh::NODES; q += ADV_BLOCK) {
+            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
+            const int gi = 2 * (bi.i0 - 1) + wx, gj = 2 * (bi.j0 - 1) + wy, gk = D == 3 ? 2 * (bi.k0 - 1) + wz : 0;
+            if (gi >= 0 && gi < m.nnx && gj >= 0 && gj < m.nny && gk >= 0 && gk < (D == 3 ? m.nnz : 1))
+                s_w[q] = Ug[gi + (int64_t)m.nnx * (gj + (int64_t)m.nny * gk)];
         }
-        for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) s_cnt[q] = 0;
+        for (int q = threadIdx.x; q < Sh::CELLS; q += ADV_BLOCK) s_cnt[q] = 0;
         if (threadIdx.x < 64) {
             // particle runs of the block's rows (in the buffer being written) and their prefix
             const int r = threadIdx.x;
@@ -415,8 +441,9 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
                 tn_[a] = cur.xr[a * cap + sn];
             }
         };
-        if ((int)threadIdx.x < total) fetch(threadIdx.x);
-        for (int f = threadIdx.x; f < total; f += BLOCK) {
+        if (PIC_BLK_PREFETCH && (int)threadIdx.x < total) fetch(threadIdx.x);
+        for (int f = threadIdx.x; f < total; f += ADV_BLOCK) {
+            if (!PIC_BLK_PREFETCH) fetch(f);
             const int r = rn, p = pn, sidx = sn;
             const int32_t K = Kn;
             double x[3], t[3];
@@ -425,9 +452,9 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
                 x[a] = xn_[a];
                 t[a] = tn_[a];
             }
-            if (f + BLOCK < total) fetch(f + BLOCK);
+            if (PIC_BLK_PREFETCH && f + ADV_BLOCK < total) fetch(f + ADV_BLOCK);
             bool near = false;
-            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Cg, s_w, b0, dt, x, t, (uint32_t)K, near);
+            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Ug, s_w, b0, dt, x, t, (uint32_t)K, near);
             if (key != LOST || FUSED) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
@@ -460,7 +487,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
             st_near += near;
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < Sh::CELLS; q += BLOCK) {
+        for (int q = threadIdx.x; q < Sh::CELLS; q += ADV_BLOCK) {
             const int ci = q % BX, r = q / BX, cj = r % BY, ck = r / BY;
             if (ci < nx && cj < ny && ck < nz)
                 P.scr.n_stay[(bi.i0 + ci) + m.n[0] * ((bi.j0 + cj) + m.n[1] * (D == 3 ? bi.k0 + ck : 0))] = s_cnt[q];
@@ -471,71 +498,6 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect_blk(const Prob
         flush_stats(P.scr.stats, ST_NEAR, st_near, nullptr);
         __syncthreads();
     }
-}
-
-// Monomial coefficients of every cell of a structured mesh from the repacked
-// nodal field (double precision), stored in both precisions.
-template <int D>
-__global__ __launch_bounds__(BLOCK) void k_mono_coeffs(const MeshDev m, const void *u64, double *c64, float *c32)
-{
-    const int64_t K = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (K >= m.n_cells) return;
-    constexpr int NC = Mono<D>::NCOEF, STRIDE = Mono<D>::STRIDE;
-    const double M[3][3] = {{1.0, 0.0, 0.0}, {-3.0, 4.0, -1.0}, {2.0, -4.0, 2.0}};
-    int ijk[3];
-    cell_ijk(m, K, ijk);
-    double out[STRIDE];
-    for (int q = 0; q < STRIDE; ++q) out[q] = 0.0;
-    for (int comp = 0; comp < D; ++comp) {
-        double v[27];
-        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
-            for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) {
-                    const int64_t g = (2 * ijk[0] + a) + (int64_t)m.nnx * ((2 * ijk[1] + b) + (int64_t)m.nny * (2 * ijk[2] + cc));
-                    double val;
-                    if constexpr (D == 3) {
-                        const double4 nv = ((const double4 *)u64)[g];
-                        val = comp == 0 ? nv.x : (comp == 1 ? nv.y : nv.z);
-                    } else {
-                        const double2 nv = ((const double2 *)u64)[g];
-                        val = comp == 0 ? nv.x : nv.y;
-                    }
-                    v[a + 3 * b + 9 * cc] = val;
-                }
-        // change of basis along x, then y, then z
-        double w[27];
-        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
-            for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) {
-                    double acc = 0.0;
-                    for (int i = 0; i < 3; ++i) acc += M[a][i] * v[i + 3 * b + 9 * cc];
-                    w[a + 3 * b + 9 * cc] = acc;
-                }
-        for (int cc = 0; cc < (D == 3 ? 3 : 1); ++cc)
-            for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) {
-                    double acc = 0.0;
-                    for (int i = 0; i < 3; ++i) acc += M[b][i] * w[a + 3 * i + 9 * cc];
-                    v[a + 3 * b + 9 * cc] = acc;
-                }
-        if constexpr (D == 3) {
-            for (int cc = 0; cc < 3; ++cc)
-                for (int b = 0; b < 3; ++b)
-                    for (int a = 0; a < 3; ++a) {
-                        double acc = 0.0;
-                        for (int i = 0; i < 3; ++i) acc += M[cc][i] * v[a + 3 * b + 9 * i];
-                        w[a + 3 * b + 9 * cc] = acc;
-                    }
-            for (int q = 0; q < 27; ++q) out[comp * 27 + q] = w[q];
-        } else {
-            for (int q = 0; q < 9; ++q) out[comp * 9 + q] = v[q];
-        }
-    }
-    for (int q = 0; q < STRIDE; ++q) {
-        c64[K * STRIDE + q] = out[q];
-        c32[K * STRIDE + q] = (float)out[q];
-    }
-    (void)NC;
 }
 
 // ===========================================================================
