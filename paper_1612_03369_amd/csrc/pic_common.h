@@ -666,9 +666,10 @@ __device__ __forceinline__ void cell_centre(const MeshDev &m, int64_t K, double 
 
 // Closest vertex of cell K to y.
 template <int D, int KIND>
-__device__ __forceinline__ void closest_vertex(const MeshDev &m, int64_t K, const double *y, double *v)
+__device__ __forceinline__ int closest_vertex(const MeshDev &m, int64_t K, const double *y, double *v)
 {
     double best = 1e300;
+    int corner = 0;
     for (int q = 0; q < (1 << D); ++q) {
         double t[3] = {(double)(q & 1), (double)((q >> 1) & 1), (double)((q >> 2) & 1)};
         double p[3];
@@ -677,18 +678,21 @@ __device__ __forceinline__ void closest_vertex(const MeshDev &m, int64_t K, cons
         for (int a = 0; a < D; ++a) d += (p[a] - y[a]) * (p[a] - y[a]);
         if (d < best) {
             best = d;
+            corner = q;
             for (int a = 0; a < D; ++a) v[a] = p[a];
         }
     }
+    return corner;
 }
 
 /*
  * Locate y starting from cell `hint`.  Uniform meshes: closed form (the cell is
  * floor((y - lo)/h); the result equals what the neighbour search would find
  * since the owning cell is unique).  Displaced and octree meshes: in-cell test
- * of the hint, then the hint's vertex neighbours in descending order of
- * (y - v).(c_K' - v) with v the hint's vertex closest to y, then the global
- * search.  Returns false when y is outside the closed domain.
+ * of the hint; then the cells that share the hint's vertex v closest to y, in
+ * descending order of (y - v).(c_K' - v); then the global search (brute force
+ * on displaced meshes, the finest-level lookup table on octrees).  Returns
+ * false when y is outside the closed domain.
  */
 template <int D, int KIND>
 __device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_t hint, int32_t &K, double *t,
@@ -717,61 +721,74 @@ __device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_
             for (int a = 0; a < D; ++a) t[a] = tt[a];
             return true;
         }
-        // vertex neighbours ordered by descending a.b
+        // Cells sharing the hint's vertex v closest to y, in descending order
+        // of a.b with a = y - v and b = c_K' - v (ties: lower cell index
+        // first), then the global search.  The order is walked without a
+        // candidate list: each try takes the best candidate after the
+        // previous one.
         double v[3], av[3];
-        closest_vertex<D, KIND>(m, hint, y, v);
+        const int corner = closest_vertex<D, KIND>(m, hint, y, v);
         for (int a = 0; a < D; ++a) av[a] = y[a] - v[a];
-        int32_t cand[MAX_NBR];
-        double score[MAX_NBR];
-        int nc = 0;
-        if constexpr (KIND == MESH_DISPLACED) {
-            int ijk[3];
-            cell_ijk(m, hint, ijk);
-            for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        if (!dx && !dy && !dz) continue;
-                        int i = ijk[0] + dx, j = ijk[1] + dy, k = ijk[2] + dz;
-                        if (i < 0 || j < 0 || k < 0 || i >= m.n[0] || j >= m.n[1] || (D == 3 && k >= m.n[2]))
-                            continue;
-                        cand[nc++] = (int32_t)(i + (int64_t)m.n[0] * (j + (int64_t)m.n[1] * k));
+        double ps = 0.0;
+        int32_t pc = -1;
+        for (int tried = 0; tried < (1 << D); ++tried) {
+            int32_t bc = -1;
+            double bs = 0.0;
+            auto consider = [&](int32_t c) {
+                double cc[3];
+                cell_centre<D, KIND>(m, c, cc);
+                double sc = 0.0;
+                for (int a = 0; a < D; ++a) sc += av[a] * (cc[a] - v[a]);
+                const bool after = pc < 0 || sc < ps || (sc == ps && c > pc);
+                if (after && (bc < 0 || sc > bs || (sc == bs && c < bc))) {
+                    bc = c;
+                    bs = sc;
+                }
+            };
+            if constexpr (KIND == MESH_OCTREE) {
+                // v on the finest lattice; the leaves sharing v are those
+                // holding the (up to) eight finest cells around it
+                const int n = (int)m.n_cells, fine = 1 << m.max_level;
+                const int sh = 1 << (m.max_level - (int)m.level[hint]);
+                int vi[3];
+                for (int a = 0; a < 3; ++a) vi[a] = m.anchor[a * n + hint] + ((corner >> a) & 1) * sh;
+                for (int o = 0; o < 8; ++o) {
+                    const int f0 = vi[0] - 1 + (o & 1), f1 = vi[1] - 1 + ((o >> 1) & 1), f2 = vi[2] - 1 + (o >> 2);
+                    if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= fine || f1 >= fine || f2 >= fine) continue;
+                    const int32_t c = m.fine[f0 + (int64_t)fine * (f1 + (int64_t)fine * f2)];
+                    if (c != hint) consider(c);
+                }
+            } else {
+                // structured: the neighbours across v are offset by 0 or by
+                // the direction of v's corner along each axis
+                int ijk[3];
+                cell_ijk(m, hint, ijk);
+                for (int pat = 1; pat < (1 << D); ++pat) {
+                    int q[3] = {ijk[0], ijk[1], ijk[2]};
+                    bool ok = true;
+                    for (int a = 0; a < D; ++a) {
+                        if ((pat >> a) & 1) q[a] += ((corner >> a) & 1) ? 1 : -1;
+                        ok &= (q[a] >= 0) & (q[a] < m.n[a]);
                     }
-        } else {
-            int b = m.nbr_off[hint], e = m.nbr_off[hint + 1];
-            for (int q = b; q < e && nc < MAX_NBR; ++q) cand[nc++] = m.nbr[q];
-        }
-        for (int q = 0; q < nc; ++q) {
-            double c[3];
-            cell_centre<D, KIND>(m, cand[q], c);
-            double s = 0.0;
-            for (int a = 0; a < D; ++a) s += av[a] * (c[a] - v[a]);
-            score[q] = s;
-        }
-        // selection order: descending score, ties by lower index
-        for (int tried = 0; tried < nc; ++tried) {
-            int bq = -1;
-            for (int q = 0; q < nc; ++q) {
-                if (cand[q] < 0) continue;
-                if (bq < 0 || score[q] > score[bq] || (score[q] == score[bq] && cand[q] < cand[bq])) bq = q;
+                    if (ok) consider((int32_t)(q[0] + (int64_t)m.n[0] * (q[1] + (int64_t)m.n[1] * q[2])));
+                }
             }
-            int32_t c = cand[bq];
-            cand[bq] = -1;
+            if (bc < 0) break;
             ls.searched++;
-            bool ok = map_to_ref<D, KIND>(m, c, y, tt);
-            if (!ok) {
+            if (!map_to_ref<D, KIND>(m, bc, y, tt)) {
                 ls.newton_fail++;
-                continue;
-            }
-            if (ref_inside<D, KIND>(m, c, tt)) {
+            } else if (ref_inside<D, KIND>(m, bc, tt)) {
                 if (tried == 0) ls.first_try++;
-                K = c;
+                K = bc;
                 for (int a = 0; a < D; ++a) t[a] = tt[a];
                 return true;
             }
+            ps = bs;
+            pc = bc;
         }
         ls.fallback++;
         if constexpr (KIND == MESH_OCTREE) {
-            int32_t c = octree_lookup(m, y);
+            const int32_t c = octree_lookup(m, y);
             map_to_ref<D, KIND>(m, c, y, tt);
             K = c;
             for (int a = 0; a < D; ++a) t[a] = tt[a];
