@@ -279,7 +279,7 @@ def bench_octree(args):
     cap = int(n0 * 1.1) + 1_000_000
     p.allocate(cap, n_prop=cfg["n_prop"], prop_dtype="float64")
     log(f"[bench] octree: {p.n_cells} leaves, {p.n_nodes} nodes, {n0} particles, set-up {time.perf_counter() - t0:.1f} s")
-    dt = cfg["cfl"] * 2.0 ** -cfg["max_level"]
+    dt = cfg["dt"]
     steps = min(cfg["steps"], max(args.steps, 1))
 
     def run(timed):

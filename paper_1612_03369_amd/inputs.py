@@ -353,9 +353,10 @@ def config3():
     f = FourierField(3, seed=2, tangential=False)
     counts = config3_counts(level.shape[0])
     counts, xr, ids = draw_reference_particles(counts, 3, seed=4 + 1000)
+    # the finest leaves (edge 2^-7) bind the step: dt = CFL * h_min / max|u| with max|u| = 1 at the nodes
     return dict(name="octree-shell-l3..7-rk2", level=level, anchor=anchor, max_level=7, field=f,
                 counts=counts, xr=xr, ids=ids, scheme=2, steps=50, n_prop=1, prop_dtype=np.float64,
-                pop_min=8, pop_max=64, pop_seed=40, cfl=0.5)
+                pop_min=8, pop_max=64, pop_seed=40, cfl=0.5, dt=0.5 * 2.0 ** -7)
 
 
 def config4_problem(p: int):

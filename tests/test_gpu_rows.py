@@ -90,14 +90,26 @@ def test_linear_least_squares_matches_oracle(L):
     p.advance(0.5 / 6, 3, L.PIC_RK2, L.PIC_F64)
     out, xbar, cnt = p.interpolate(L.PIC_INTERP_LINEAR_LS)
     g = p.numpy()
-    coef_o, xbar_o = O.linear_least_squares(cfg["mesh"].n_cells, 3, g["cell_start"], g["xr"], g["prop"])
+    # the oracle fits its own store after its own 3 steps
+    om, st = oracle_store(cfg)
+    near, _ = oracle_run_tracking(om, cfg["U"], 0.5 / 6, 2, 3, st)
+    o = st.view()
+    compare_stores(g, o, near)
+    coef_o, xbar_o = O.linear_least_squares(cfg["mesh"].n_cells, 3, st.cell_start, o["xr"], o["prop"])
     c = cnt.cpu().numpy()
     assert np.array_equal(c, np.diff(g["cell_start"]))
     og, xg = out.cpu().numpy(), xbar.cpu().numpy()
-    ok = c > 0
-    assert np.all(np.isnan(og[~ok]))
-    assert np.allclose(xg[ok], xbar_o[ok], rtol=0, atol=1e-14)
+    # cells holding a near-face particle may hold different sets on the two sides
+    skip = np.zeros(c.size, bool)
+    near_arr = np.array(sorted(near), dtype=np.int64)
+    skip[g["cell"][np.isin(g["id"].astype(np.int64), near_arr)]] = True
+    skip[o["cell"][np.isin(o["id"].astype(np.int64), near_arr)]] = True
+    ok = (c > 0) & ~skip
+    assert np.array_equal(np.diff(st.cell_start)[~skip], c[~skip])
+    assert np.all(np.isnan(og[c == 0]))
+    assert np.allclose(xg[ok], xbar_o[ok], rtol=0, atol=1e-12)
     assert np.allclose(og[ok], coef_o[ok], rtol=1e-9, atol=1e-11)
+    _say(f"  {ok.sum()} cells compared, {skip.sum()} skipped (near-face particles)")
     p.close()
 
 
@@ -169,18 +181,28 @@ def test_adjoint_matches_oracle_gradient(L, scheme):
     flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, scheme, ckpt)
     U = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device, requires_grad=True)
     xT = advect(U, flow)
+    # targets: the oracle's own forward run plus noise, indexed by id
+    om, st = oracle_store(cfg)
+    v = st.view()
+    _, fin = oracle_store(cfg)
+    O.run(om, cfg["U"], dt, scheme, steps, fin)
+    f = fin.view()
+    n_id = xT.shape[1]
+    x_or = np.full((3, n_id), np.nan)
+    x_or[:, f["id"]] = f["x"]
     rng = np.random.default_rng(7)
-    tgt = torch.tensor(xT.detach().cpu().numpy() + 0.01 * rng.standard_normal(xT.shape), device=p.device)
-    mask = ~torch.isnan(xT[0])
+    tgt_np = x_or + 0.01 * rng.standard_normal(x_or.shape)
+    live_g = ~np.isnan(xT.detach().cpu().numpy()[0])
+    m_id = live_g & ~np.isnan(x_or[0])
+    tgt = torch.tensor(np.nan_to_num(tgt_np), device=p.device)
+    mask = torch.tensor(m_id, device=p.device)
     nv = int(mask.sum())
     loss = ((xT - tgt)[:, mask] ** 2).sum() / nv
     loss.backward()
     g = U.grad.cpu().numpy()
     # oracle: per-particle reverse sweep from the initial state
-    om, st = oracle_store(cfg)
-    v = st.view()
-    tg = tgt.cpu().numpy()[:, v["id"]]
-    m = mask.cpu().numpy()[v["id"]].astype(np.uint8)
+    tg = np.nan_to_num(tgt_np)[:, v["id"]]
+    m = m_id[v["id"]].astype(np.uint8)
     Lo, dUo, lost = O.adjoint(om, cfg["U"], dt, scheme, steps, v["x"], v["cell"], v["xr"], tg, m)
     assert abs(float(loss) - Lo) <= 1e-12 * abs(Lo)
     assert np.abs(g - dUo).max() <= 1e-10 * np.abs(dUo).max(), np.abs(g - dUo).max() / np.abs(dUo).max()
