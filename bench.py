@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+REPO = os.path.dirname(os.path.abspath(__file__))
+# byte counters of the dominant kernel, taken by --summarize-traffic from two rocprofv3 --pmc runs
+TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_gather_advect_uniform64_rk4_f32.json")
+DOMINANT_KERNEL = "k_advect_blk<3, 4, float, 4, 4, 4, true>"
+COPY_BYTES = 64 * 1024 * 1024 * 4          # the calibration copy below: 256 MiB read, 256 MiB written
 
 
 def log(msg):
@@ -33,6 +38,96 @@ def log(msg):
 
 # algorithmic bytes per particle and launch (see the design notes): d = 3,
 # 3 float properties, int32 cell/key/src, uint32 id
+def source_digest():
+    """sha256 over the library sources: byte counters are valid only for the code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(REPO, "paper_1612_03369_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(REPO, "include", "pic.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def _pmc_per_dispatch(run_dir, counter):
+    """{kernel name: [(counter value of one dispatch in KiB, duration ns), ...]} of a rocpd database."""
+    import glob
+    import sqlite3
+    out = {}
+    for db in glob.glob(os.path.join(run_dir, "**", "*results.db"), recursive=True):
+        con = sqlite3.connect(db)
+        q = ("select kernel_name, dispatch_id, sum(value), avg(duration) from counters_collection "
+             "where counter_name = ? group by dispatch_id")
+        for name, _, total, dur in con.execute(q, (counter,)):
+            out.setdefault(name, []).append((total, dur))
+        con.close()
+    return out
+
+
+def _copy_kib(per_kernel):
+    """Counter value of the 256 MiB copies: median over the copy dispatches within half of the largest."""
+    import statistics
+    vals = [v for k, lst in per_kernel.items() if "copyBuffer" in k for v, _ in lst]
+    top = max(vals)
+    return statistics.median(v for v in vals if v >= 0.5 * top)
+
+
+def summarize_traffic(fetch_dir, write_dir, command):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE and WRITE_SIZE runs, each scaled by what the
+    same counter reads for the 256 MiB device copy of the same run."""
+    fetch = _pmc_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _pmc_per_dispatch(write_dir, "WRITE_SIZE")
+    dom = [k for k in fetch if DOMINANT_KERNEL in k]
+    if len(dom) != 1:
+        raise SystemExit(f"dominant kernel not found once in {fetch_dir}: {dom}")
+    dom = dom[0]
+    f_n = len(fetch[dom])
+    f_kib = sum(v for v, _ in fetch[dom]) / f_n
+    f_dur = sum(d for _, d in fetch[dom]) / f_n
+    w_kib = sum(v for v, _ in write[dom]) / len(write[dom])
+    cp = "__amd_rocclr_copyBuffer"
+    cf_kib = _copy_kib(fetch)
+    cw_kib = _copy_kib(write)
+    f_scale = COPY_BYTES / (cf_kib * 1024.0)
+    w_scale = COPY_BYTES / (cw_kib * 1024.0)
+    rec = {"kernel": dom, "dispatches": f_n, "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+           "copy_kernel": cp, "copy_bytes_each_way": COPY_BYTES, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "traffic_bytes_per_launch": f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale,
+           "mean_duration_ns_under_counters": f_dur, "source_sha256": source_digest(), "command": command}
+    print(json.dumps(rec, indent=1))
+
+
+def summarize_trace(trace_dir, title, command):
+    """Per-kernel call count, total and mean duration of a rocprofv3 --kernel-trace --stats run."""
+    import glob
+    import sqlite3
+    print(f"# rocprofv3 kernel-trace summary: {title}")
+    print(f"# command: {command}")
+    print("# columns: kernel, calls, total_us, average_us, percent")
+    for db in glob.glob(os.path.join(trace_dir, "**", "*results.db"), recursive=True):
+        con = sqlite3.connect(db)
+        for name, n, tot, avg, pct in con.execute(
+                "select name, total_calls, total_duration, average, percentage from top_kernels"):
+            print(f"{name}\t{n}\t{tot:.1f}\t{avg:.3f}\t{pct:.2f}")
+        con.close()
+
+
+def measured_traffic():
+    """Bytes per launch of the dominant kernel from the committed counter summary, or None when the summary is
+    missing or was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, "no counter summary"
+    if rec.get("source_sha256") != source_digest():
+        return None, "counter summary taken on other sources"
+    return rec["traffic_bytes_per_launch"], TRAFFIC_FILE
+
+
 def bytes_per_particle(kernel, dim=3, prop_bytes=12):
     x = 8 * dim
     return {
@@ -109,6 +204,7 @@ def run_main(args):
     achieved = bytes_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e9
     step_bytes = avg_particles * (bytes_per_particle("gather_advect") + bytes_per_particle("place")) + field_bytes
     step_ms = 1e3 * elapsed / args.steps
+    traffic, traffic_src = measured_traffic()
     line = {
         "metric": "particle-steps/s (advect+locate+sort)",
         "value": value,
@@ -125,8 +221,9 @@ def run_main(args):
         "config": {"workload": cfg["name"], "cells": mesh.n_cells, "particles": n0, "scheme": "rk4",
                    "dt": dt, "eval": "f32", "n_prop": 3, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": kernels[dom]["avg_us"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic if dom == "gather_advect" else None,
+                     "traffic_source": traffic_src, "bytes_per_launch": bytes_launch,
+                     "avg_launch_us": kernels[dom]["avg_us"]},
         "step_hbm_frac": step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
         "stats": st,
@@ -351,7 +448,17 @@ def main():
     ap.add_argument("--extras", default="adjoint,batch,octree", help="comma list: adjoint,batch,octree ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="print the counter summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "TITLE", "COMMAND"),
+                    help="print the per-kernel summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the particle path has no "
               "multi-GPU form (one MI355X holds the whole mesh and particle set).", file=sys.stderr)

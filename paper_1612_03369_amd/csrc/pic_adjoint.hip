@@ -99,7 +99,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
     const double dt = P.dt;
     auto Ug = (gptr<V>)P.u64;
     const int64_t nn = m.n_nodes;
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
         const BlockItem bi = work[w];
         const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
         const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);

@@ -386,9 +386,9 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
     if (unsorted)
         LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     else
-        LAUNCH(c, "place", k_place, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
-    LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
-    LAUNCH(c, "gather", k_gather, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+        LAUNCH(c, "place", k_place, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+    LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+    LAUNCH(c, "gather", k_gather, (unsigned)xcd_span(c->n_rp), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, count_step);
     return PIC_OK;
 }
@@ -430,13 +430,13 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
     const int pr = prec == PIC_F32;
     BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false);
     BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true);
-    LAUNCH(c, "advect", fa, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+    LAUNCH(c, "advect", fa, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0);
         if (s) return s;
-        LAUNCH(c, "place", k_place, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
-        LAUNCH(c, "fix", k_fix, (unsigned)c->n_rc, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
-        LAUNCH(c, "gather_advect", ff, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
+        LAUNCH(c, "place", k_place, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+        LAUNCH(c, "gather_advect", ff, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
         LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, 1);
     }
     return enqueue_sort(c, dp, 1);
@@ -447,13 +447,13 @@ pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
     if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
         BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false);
         const int pr = prec == PIC_F32;
-        LAUNCH(c, "advect", f, (unsigned)c->n_blk[pr], ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
+        LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
                c->n_blk[pr]);
         return enqueue_sort(c, dp, 1);
     }
     AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind);
     if (!f) return fail(c, PIC_EINVAL, "unsupported combination dim=%d scheme=%d kind=%d", c->mesh.dim, scheme, c->mesh.kind);
-    LAUNCH(c, "advect", f, (unsigned)c->n_work, BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+    LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
     return enqueue_sort(c, dp, 1);
 }
 

@@ -800,6 +800,19 @@ __device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware work mapping.  Workgroups are dealt to the eight XCDs round robin
+// (workgroup b runs on XCD b mod 8) and each XCD has its own L2.  Workgroup b
+// takes item (b mod 8) * ceil(n/8) + b / 8, so every XCD walks one contiguous
+// eighth of a spatially ordered work list: neighbouring items (shared halo
+// nodes, particles moving between neighbouring cells, cache lines split
+// between neighbouring segments) meet in the same L2.  Launch xcd_span(n)
+// workgroups; items >= n are skipped.
+// ---------------------------------------------------------------------------
+constexpr int N_XCD = 8;
+__host__ __device__ inline int xcd_span(int n) { return N_XCD * ((n + N_XCD - 1) / N_XCD); }
+__device__ __forceinline__ int xcd_item(int b, int n) { return (b % N_XCD) * ((n + N_XCD - 1) / N_XCD) + b / N_XCD; }
+
+// ---------------------------------------------------------------------------
 // workgroup helpers
 // ---------------------------------------------------------------------------
 // Exclusive scan of 0/1 flags over a 256-thread workgroup; returns the prefix

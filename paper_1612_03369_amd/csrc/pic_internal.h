@@ -32,7 +32,7 @@ struct WorkItem {
 // Block of cells [i0, i0+BX) x [j0, j0+BY) x [k0, k0+BZ) of a uniform mesh
 // (clipped to the mesh); its particles are BY*BZ runs of consecutive cells.
 struct BlockItem {
-    int32_t problem;
+    int32_t problem;         // -1: empty slot (no work)
     int32_t i0, j0, k0;
 };
 struct ScanItem {

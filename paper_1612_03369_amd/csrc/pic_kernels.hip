@@ -163,7 +163,9 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
                                                                   const WorkItem *__restrict__ work, int n_work)
 {
     __shared__ int s_cnt[MAX_TILE];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
         const WorkItem wi = work[w];
         const ProblemDev &P = probs[wi.problem];
         const MeshDev &m = P.mesh;
@@ -371,8 +373,11 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
     __shared__ int s_cnt[Sh::CELLS];
     __shared__ int s_pre[Sh::ROWS + 1];
     __shared__ int s_beg[Sh::ROWS];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
         const BlockItem bi = work[w];
+        if (bi.problem < 0) continue;            // empty slot of a padded list
         const ProblemDev &P = probs[bi.problem];
         const MeshDev &m = P.mesh;
         const StoreDev cur = P.store[P.cur];
@@ -639,7 +644,9 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
     __shared__ int s_cs[MAX_TILE + 1];
     __shared__ int s_base[MAX_TILE];
     __shared__ int s_wave[BLOCK / 64];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
         const WorkItem wi = work[w];
         const ProblemDev &P = probs[wi.problem];
         const StoreDev cur = P.store[P.cur];
@@ -706,7 +713,9 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                int n_items)
 {
-    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_items); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_items);
+        if (w >= n_items) continue;
         const RangeItem it = items[w];
         const ProblemDev &P = probs[it.problem];
         const int64_t K = it.begin + threadIdx.x;
@@ -748,7 +757,9 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
 __global__ __launch_bounds__(BLOCK) void k_gather(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                   int n_items)
 {
-    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    for (int wb = blockIdx.x; wb < xcd_span(n_items); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_items);
+        if (w >= n_items) continue;
         const RangeItem it = items[w];
         const ProblemDev &P = probs[it.problem];
         const StoreDev cur = P.store[P.cur];
