@@ -336,21 +336,33 @@ def bench_batch(args):
     t_single = time.perf_counter() - t
     ps_single = sum(q.stats()["particle_steps"] for q in probs)
     bt = Batch(probs)
-    reseed()
-    bt.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 20)   # graph build + warm
-    torch.cuda.synchronize()
+    dts, schemes = [c["dt"] for c in cfgs], [c["scheme"] for c in cfgs]
+
+    def run_batch():
+        reseed()
+        bt.advance(dts, schemes, 20)                 # graph build + warm
+        torch.cuda.synchronize()
+        reseed()
+        t = time.perf_counter()
+        bt.advance(dts, schemes, 20)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, sum(q.stats()["particle_steps"] for q in probs)
+
+    t_default, _ = run_batch()                       # default cell-block shapes
     reseed()
     t = time.perf_counter()
-    bt.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 20)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t
-    ps_batch = sum(q.stats()["particle_steps"] for q in probs)
+    tuned = bt.tune(dts, schemes, trials=3)          # the library's autotuner
+    t_tune = time.perf_counter() - t
+    t_batch, ps_batch = run_batch()
     bt.close()
     for q in probs:
         q.close()
     log(f"[bench] batch: {len(cfgs)} problems, {total} particles: per-problem {t_single * 1e3:.1f} ms, "
-        f"batched graph {t_batch * 1e3:.1f} ms")
+        f"batched graph {t_default * 1e3:.1f} ms (default shapes), {t_batch * 1e3:.1f} ms (tuned {tuned['variants']}, "
+        f"tuning {t_tune * 1e3:.0f} ms)")
     return {"problems": len(cfgs), "particles": total, "per_problem_ms": t_single * 1e3, "batched_ms": t_batch * 1e3,
+            "batched_default_shapes_ms": t_default * 1e3, "tuning_ms": t_tune * 1e3,
+            "tuned_variants": tuned["variants"], "tuned_times_ms": tuned["times_ms"],
             "speedup": t_single / t_batch, "particle_steps_per_s": ps_batch / t_batch,
             "per_problem_particle_steps_per_s": ps_single / t_single}
 

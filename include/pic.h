@@ -238,6 +238,22 @@ PIC_API pic_status pic_batch_create(pic_batch **out, int32_t n, pic_ctx *const *
                             void *hip_stream);
 /* n_steps steps of every problem with its own dt / scheme (F64 evaluation). */
 PIC_API pic_status pic_batch_advance(pic_batch *b, const double *dt, const int32_t *scheme, int32_t n_steps);
+/* Workgroup-per-cell-block schedule of the batched advect, per group
+ * g = 3 * (dim == 3) + (0 Euler, 1 RK2, 2 RK4): variant[g] selects the cell
+ * block one workgroup advances (2D: 8x8, 8x4, 16x8 cells; 3D: 4x4x4,
+ * 4x2x2, 4x4x2).  Results do not depend on it (the block's LDS window and the
+ * global field give identical values).  Values outside 0..2 -> PIC_EINVAL. */
+PIC_API pic_status pic_batch_set_schedule(pic_batch *b, const int32_t variant[6]);
+/* Autotuner: for each group present, time `trials` launches of the group's
+ * advect per candidate block shape on the problems' own particles and keep
+ * the fastest.  Locations, reference locations and statistics are restored
+ * afterwards, so the problems are left as they were.  Synchronises.
+ * variant_out (host [6], may be NULL) receives the choice; time_ms_out (host
+ * [18], may be NULL) the mean launch time of group g, shape v at [3g + v]
+ * (-1 for groups without problems).  Takes dt / scheme like
+ * pic_batch_advance.  Needs device memory for one copy of the locations. */
+PIC_API pic_status pic_batch_tune(pic_batch *b, const double *dt, const int32_t *scheme, int32_t trials,
+                                  int32_t variant_out[6], double time_ms_out[18]);
 PIC_API void pic_batch_destroy(pic_batch *b);
 PIC_API const char *pic_batch_last_error(const pic_batch *b);
 

@@ -31,7 +31,8 @@ EXPORTS = [
     "pic_seed_reference", "pic_seed_positions", "pic_advance", "pic_population", "pic_interpolate",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
-    "pic_batch_create", "pic_batch_advance", "pic_batch_destroy", "pic_batch_last_error",
+    "pic_batch_create", "pic_batch_advance", "pic_batch_set_schedule", "pic_batch_tune", "pic_batch_destroy",
+    "pic_batch_last_error",
 ]
 
 
@@ -101,6 +102,8 @@ def load(path: str | None = None):
             "pic_profile_read": (S, [P, C.c_char_p, P, P]),
             "pic_batch_create": (S, [C.POINTER(P), I32, P, P, P]),
             "pic_batch_advance": (S, [P, P, P, I32]),
+            "pic_batch_set_schedule": (S, [P, P]),
+            "pic_batch_tune": (S, [P, P, P, I32, P, P]),
             "pic_batch_destroy": (None, [P]),
             "pic_batch_last_error": (C.c_char_p, [P]),
         }

@@ -294,6 +294,52 @@ class Batch:
         L.check(self.lib.pic_batch_advance(self.h, dt, sc, int(n_steps)), batch=self.h)
         cur.wait_stream(self.stream)
 
+    GROUPS = ("2d-euler", "2d-rk2", "2d-rk4", "3d-euler", "3d-rk2", "3d-rk4")
+    SHAPES = {2: ((8, 8), (8, 4), (16, 8)), 3: ((4, 4, 4), (4, 2, 2), (4, 4, 2))}
+
+    def set_schedule(self, variants):
+        """Cell-block shape index (0..2) per group, in GROUPS order."""
+        v = (C.c_int32 * 6)(*[int(x) for x in variants])
+        L.check(self.lib.pic_batch_set_schedule(self.h, v), batch=self.h)
+
+    def signature(self, schemes):
+        """What the schedule depends on: per problem dim, cells, capacity and scheme."""
+        return [[p.dim, int(p.n_cells), int(p.store.capacity), int(s)] for p, s in zip(self.problems, schemes)]
+
+    def tune(self, dts, schemes, trials=3, cache=None):
+        """Pick the fastest cell-block shape per group (the library's autotuner) and return
+        {"variants": [...], "times_ms": {...}}.  With `cache` (a JSON path) a stored choice for the
+        same signature is applied without timing, and a new choice is stored."""
+        import json
+        import os
+        sig = self.signature(schemes)
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                rec = json.load(f)
+            if rec.get("signature") == sig:
+                self.set_schedule(rec["variants"])
+                return rec
+        n = len(self.problems)
+        dt = (C.c_double * n)(*[float(v) for v in dts])
+        sc = (C.c_int32 * n)(*[int(v) for v in schemes])
+        var = (C.c_int32 * 6)()
+        tms = (C.c_double * 18)()
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.problems[0].device)
+        self.stream.wait_stream(cur)
+        L.check(self.lib.pic_batch_tune(self.h, dt, sc, int(trials), var, tms), batch=self.h)
+        cur.wait_stream(self.stream)
+        times = {}
+        for g, name in enumerate(self.GROUPS):
+            if tms[3 * g] >= 0:
+                d = 2 if g < 3 else 3
+                times[name] = {"x".join(map(str, self.SHAPES[d][v])): tms[3 * g + v] for v in range(3)}
+        rec = {"signature": sig, "variants": list(var), "times_ms": times}
+        if cache:
+            with open(cache, "w") as f:
+                json.dump(rec, f)
+        return rec
+
     def close(self):
         if getattr(self, "h", None) is not None:
             self.lib.pic_batch_destroy(self.h)

@@ -261,6 +261,27 @@ inline const int *block_shape(int dim, int prec)
     return dim == 2 ? BLK2 : (prec == PIC_F32 ? BLK3_F32 : BLK3_F64);
 }
 
+// Candidate cell-block shapes of the batched (double-precision) advect, one
+// of which pic_batch_tune picks per (dim, scheme) group; shape 0 is the
+// default above.
+constexpr int N_SHAPES = 3;
+constexpr int SHAPES2[N_SHAPES][3] = {{8, 8, 1}, {8, 4, 1}, {16, 8, 1}};
+constexpr int SHAPES3[N_SHAPES][3] = {{4, 4, 4}, {4, 2, 2}, {4, 4, 2}};
+static_assert(SHAPES2[0][0] == BLK2[0] && SHAPES2[0][1] == BLK2[1], "shape 0 is the default");
+static_assert(SHAPES3[0][0] == BLK3_F64[0] && SHAPES3[0][1] == BLK3_F64[1] && SHAPES3[0][2] == BLK3_F64[2],
+              "shape 0 is the default");
+inline const int *batch_shape(int dim, int variant) { return dim == 2 ? SHAPES2[variant] : SHAPES3[variant]; }
+
+std::vector<BlockItem> block_items_shape(const MeshDev &m, const int *b, int problem)
+{
+    std::vector<BlockItem> v;
+    const int nz = m.dim == 3 ? m.n[2] : 1, bz = m.dim == 3 ? b[2] : 1;
+    for (int k = 0; k < nz; k += bz)
+        for (int j = 0; j < m.n[1]; j += b[1])
+            for (int i = 0; i < m.n[0]; i += b[0]) v.push_back({problem, i, j, k});
+    return v;
+}
+
 std::vector<BlockItem> block_items(const MeshDev &m, int prec, int problem)
 {
     const int *b = block_shape(m.dim, prec);
@@ -413,6 +434,28 @@ template <int D, bool F = false> BlockFn block_for_scheme(int scheme, int prec)
     }
     return nullptr;
 }
+// Double-precision, unfused block advect of cell-block shape `variant` (batch).
+template <int D, int S, int V> BlockFn shape_kernel()
+{
+    if constexpr (D == 3) return k_advect_blk<3, S, double, SHAPES3[V][0], SHAPES3[V][1], SHAPES3[V][2], false>;
+    else return k_advect_blk<2, S, double, SHAPES2[V][0], SHAPES2[V][1], 1, false>;
+}
+template <int D, int S> BlockFn shape_kernel_v(int variant)
+{
+    switch (variant) {
+    case 0: return shape_kernel<D, S, 0>();
+    case 1: return shape_kernel<D, S, 1>();
+    case 2: return shape_kernel<D, S, 2>();
+    }
+    return nullptr;
+}
+BlockFn batch_block_kernel(int dim, int scheme, int variant)
+{
+    const int S = scheme == PIC_EULER ? 1 : scheme == PIC_RK2 ? 2 : 4;
+    if (dim == 2) return S == 1 ? shape_kernel_v<2, 1>(variant) : S == 2 ? shape_kernel_v<2, 2>(variant) : shape_kernel_v<2, 4>(variant);
+    return S == 1 ? shape_kernel_v<3, 1>(variant) : S == 2 ? shape_kernel_v<3, 2>(variant) : shape_kernel_v<3, 4>(variant);
+}
+
 BlockFn block_kernel(int dim, int scheme, int prec, bool fused)
 {
     if (dim == 2) return fused ? block_for_scheme<2, true>(scheme, prec) : block_for_scheme<2, false>(scheme, prec);

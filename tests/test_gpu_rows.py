@@ -129,8 +129,11 @@ def test_linear_least_squares_reproduces_linear_data(L):
 
 
 # ----------------------------------------------------------------------------
-def test_batch_bit_identical_to_single_runs(L):
-    _say("case: batch of 6 mixed problems vs single runs")
+@pytest.mark.parametrize("schedule", ["default", "tuned", "shape2"])
+def test_batch_bit_identical_to_single_runs(L, schedule):
+    """Batched steps equal single runs bit for bit, whatever cell-block schedule the
+    batch uses; the autotuner leaves the problems' state and statistics as they were."""
+    _say(f"case: batch of 6 mixed problems vs single runs, schedule {schedule}")
     from paper_1612_03369_amd.api import Batch
     cfgs = []
     for q in range(6):
@@ -140,21 +143,33 @@ def test_batch_bit_identical_to_single_runs(L):
         c["scheme"] = (2, 4)[(q // 2) % 2] if q != 5 else 1
         c["dt"] = 0.5 / n
         cfgs.append(c)
-    singles = []
+    singles, single_stats = [], []
     for c in cfgs:
         p = gpu_problem(c)
         p.advance(c["dt"], 7, c["scheme"], L.PIC_F64)
         singles.append(p.numpy())
+        single_stats.append(p.stats())
         p.close()
     probs = [gpu_problem(c) for c in cfgs]
     b = Batch(probs, tile_cells=(16, 32, 8, 16))
-    b.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 4)
-    b.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 3)
-    for p, s in zip(probs, singles):
+    dts, schemes = [c["dt"] for c in cfgs], [c["scheme"] for c in cfgs]
+    if schedule == "tuned":
+        rec = b.tune(dts, schemes, trials=2)
+        _say(f"  tuned variants {rec['variants']}")
+        assert all(0 <= v <= 2 for v in rec["variants"])
+        assert set(rec["times_ms"]) == {"2d-rk2", "2d-rk4", "3d-euler", "3d-rk2", "3d-rk4"}
+    elif schedule == "shape2":
+        b.set_schedule([2, 2, 2, 2, 2, 2])
+    b.advance(dts, schemes, 4)
+    b.advance(dts, schemes, 3)
+    for p, s, ss in zip(probs, singles, single_stats):
         g = p.numpy()
         for k in ("x", "xr", "cell", "id", "prop", "cell_start"):
             assert np.array_equal(g[k], s[k]), k
-        assert p.stats()["steps"] == 7
+        st = p.stats()
+        assert st["steps"] == 7
+        for k in ("particle_steps", "lost", "moved", "near_face"):
+            assert st[k] == ss[k], k
     b.close()
     for p in probs:
         p.close()
