@@ -360,7 +360,7 @@ template <int D, typename T> struct BlkWaves {
     static constexpr int value = D == 2 ? 1 : (sizeof(T) == 4 ? (PIC_BLK_MIN_WAVES > 0 ? PIC_BLK_MIN_WAVES : 1) : 2);
 };
 #ifndef PIC_BLK_PREFETCH
-#define PIC_BLK_PREFETCH 1          // 1: load the next particle's state while advancing this one
+#define PIC_BLK_PREFETCH 2          // 1: load the next particle's state while advancing this one; 2: also its gather source one step earlier
 #endif
 constexpr int ADV_BLOCK = PIC_ADV_THREADS;
 template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED>
@@ -371,8 +371,11 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
     using V = typename NodeVec<D, T>::type;
     __shared__ V s_w[Sh::NODES];
     __shared__ int s_cnt[Sh::CELLS];
-    __shared__ int s_pre[Sh::ROWS + 1];
-    __shared__ int s_beg[Sh::ROWS];
+    static_assert(Sh::ROWS <= 64, "one wave scans the rows of a block");
+    __shared__ int s_pre_w[ADV_BLOCK / 64][Sh::ROWS + 1];
+    __shared__ int s_beg_w[ADV_BLOCK / 64][Sh::ROWS];
+    int *s_pre = s_pre_w[threadIdx.x >> 6];      // each wave keeps its own copy of the row runs
+    int *s_beg = s_beg_w[threadIdx.x >> 6];
     for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
         const int w = xcd_item(wb, n_work);
         if (w >= n_work) continue;
@@ -390,18 +393,11 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
         const int b0[3] = {bi.i0, bi.j0, D == 3 ? bi.k0 : 0};
         const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
         const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
-        // stage the window; nodes beyond the mesh are never read (stage
-        // points are clamped to mesh cells) and are left unset
-        for (int q = threadIdx.x; q < Sh::NODES; q += ADV_BLOCK) {
-            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
-            const int gi = 2 * (bi.i0 - 1) + wx, gj = 2 * (bi.j0 - 1) + wy, gk = D == 3 ? 2 * (bi.k0 - 1) + wz : 0;
-            if (gi >= 0 && gi < m.nnx && gj >= 0 && gj < m.nny && gk >= 0 && gk < (D == 3 ? m.nnz : 1))
-                s_w[q] = Ug[gi + (int64_t)m.nnx * (gj + (int64_t)m.nny * gk)];
-        }
-        for (int q = threadIdx.x; q < Sh::CELLS; q += ADV_BLOCK) s_cnt[q] = 0;
-        if (threadIdx.x < 64) {
-            // particle runs of the block's rows (in the buffer being written) and their prefix
-            const int r = threadIdx.x;
+        {
+            // particle runs of the block's rows (in the buffer being written)
+            // and their prefix, computed by every wave for itself so that the
+            // first particles can be fetched before the window is complete
+            const int r = threadIdx.x & 63;
             int len = 0, beg = 0;
             if (r < Sh::ROWS) {
                 const int rj = r % BY, rk = r / BY;
@@ -421,7 +417,9 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
             if (r < Sh::ROWS) s_pre[r + 1] = inc;
             if (r == 0) s_pre[0] = 0;
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int total = s_pre[Sh::ROWS];
         int st_lost = 0, st_moved = 0, st_near = 0;
         // particle f of the block -> its row and position in the buffer written
@@ -446,7 +444,44 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
                 tn_[a] = cur.xr[a * cap + sn];
             }
         };
-        if (PIC_BLK_PREFETCH && (int)threadIdx.x < total) fetch(threadIdx.x);
+        // two-deep variant: the gather source of particle f + 2 BLOCK is loaded
+        // one iteration ahead of its state
+        int pA = 0, rA = 0, sA = 0;
+        auto stage_a = [&](int f) {
+            pA = locate_f(f, rA);
+            sA = FUSED ? P.scr.src[pA] : pA;
+        };
+        auto stage_b = [&]() {
+            pn = pA;
+            rn = rA;
+            sn = sA;
+            Kn = FUSED ? (int32_t)key_in[sn] : cur.cell[sn];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xn_[a] = cur.x[a * cap + sn];
+                tn_[a] = cur.xr[a * cap + sn];
+            }
+        };
+        if (PIC_BLK_PREFETCH == 2) {
+            if ((int)threadIdx.x < total) {
+                stage_a(threadIdx.x);
+                stage_b();
+            }
+            if ((int)threadIdx.x + ADV_BLOCK < total) stage_a(threadIdx.x + ADV_BLOCK);
+        } else if (PIC_BLK_PREFETCH && (int)threadIdx.x < total) {
+            fetch(threadIdx.x);
+        }
+        // stage the window (its loads overlap the first fetch); nodes beyond
+        // the mesh are never read (stage points are clamped to mesh cells)
+        // and are left unset
+        for (int q = threadIdx.x; q < Sh::NODES; q += ADV_BLOCK) {
+            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
+            const int gi = 2 * (bi.i0 - 1) + wx, gj = 2 * (bi.j0 - 1) + wy, gk = D == 3 ? 2 * (bi.k0 - 1) + wz : 0;
+            if (gi >= 0 && gi < m.nnx && gj >= 0 && gj < m.nny && gk >= 0 && gk < (D == 3 ? m.nnz : 1))
+                s_w[q] = Ug[gi + (int64_t)m.nnx * (gj + (int64_t)m.nny * gk)];
+        }
+        for (int q = threadIdx.x; q < Sh::CELLS; q += ADV_BLOCK) s_cnt[q] = 0;
+        __syncthreads();
         for (int f = threadIdx.x; f < total; f += ADV_BLOCK) {
             if (!PIC_BLK_PREFETCH) fetch(f);
             const int r = rn, p = pn, sidx = sn;
@@ -457,7 +492,12 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
                 x[a] = xn_[a];
                 t[a] = tn_[a];
             }
-            if (PIC_BLK_PREFETCH && f + ADV_BLOCK < total) fetch(f + ADV_BLOCK);
+            if (PIC_BLK_PREFETCH == 2) {
+                if (f + ADV_BLOCK < total) stage_b();
+                if (f + 2 * ADV_BLOCK < total) stage_a(f + 2 * ADV_BLOCK);
+            } else if (PIC_BLK_PREFETCH && f + ADV_BLOCK < total) {
+                fetch(f + ADV_BLOCK);
+            }
             bool near = false;
             const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Ug, s_w, b0, dt, x, t, (uint32_t)K, near);
             if (key != LOST || FUSED) {
@@ -642,6 +682,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
                                                  int n_work)
 {
     __shared__ int s_cs[MAX_TILE + 1];
+    __shared__ int s_ncs[MAX_TILE];
     __shared__ int s_base[MAX_TILE];
     __shared__ int s_wave[BLOCK / 64];
     for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
@@ -651,19 +692,30 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
         const ProblemDev &P = probs[wi.problem];
         const StoreDev cur = P.store[P.cur];
         const StoreDev nxt = P.store[1 - P.cur];
+        const uint32_t *keys = P.scr.key[P.cur];
         const int c0 = wi.c0, nt = wi.c1 - wi.c0;
-        for (int k = threadIdx.x; k <= nt; k += BLOCK) s_cs[k] = cur.cs[c0 + k];
+        for (int k = threadIdx.x; k <= nt; k += BLOCK) {
+            s_cs[k] = cur.cs[c0 + k];
+            if (k < nt) s_ncs[k] = nxt.cs[c0 + k];
+        }
         __syncthreads();
         const int p0 = s_cs[0], p1 = s_cs[nt];
+        // the key and cell of the next round are loaded while this round is placed
+        uint32_t key_n = LOST;
+        int K_n = c0;
+        if (p0 + (int)threadIdx.x < p1) {
+            key_n = keys[p0 + threadIdx.x];
+            K_n = cur.cell[p0 + threadIdx.x];
+        }
         int carry = 0;
         for (int base = p0; base < p1; base += BLOCK) {
             const int i = base + threadIdx.x;
             const bool active = i < p1;
-            uint32_t key = LOST;
-            int K = c0;
-            if (active) {
-                key = P.scr.key[P.cur][i];
-                K = cur.cell[i];
+            const uint32_t key = key_n;
+            const int K = K_n;
+            if (i + BLOCK < p1) {
+                key_n = keys[i + BLOCK];
+                K_n = cur.cell[i + BLOCK];
             }
             const int stay = active && key == (uint32_t)K;
             int total;
@@ -675,10 +727,10 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
             if (active && key != LOST) {
                 int64_t dst;
                 if (stay) {
-                    dst = (int64_t)nxt.cs[K] + (Pi - s_base[kloc]);
+                    dst = (int64_t)s_ncs[kloc] + (Pi - s_base[kloc]);
                 } else {
-                    const int r = atomicAdd(&P.scr.cursor[key], 1);
-                    dst = (int64_t)nxt.cs[key] + P.scr.n_stay[key] + r;
+                    const int64_t b = (int64_t)nxt.cs[key] + P.scr.n_stay[key];
+                    dst = b + atomicAdd(&P.scr.cursor[key], 1);
                 }
                 P.scr.src[dst] = i;
             }
