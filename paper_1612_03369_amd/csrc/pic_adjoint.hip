@@ -28,13 +28,14 @@ template <int D, int BX, int BY, int BZ> struct NodeWin {
     static constexpr int ROWS = BY * (D == 3 ? BZ : 1);
 };
 
-// reference gradient Gr[c][r] = d u_c / d t_r of the nodal field at (ijk, t) and
-// the nodal basis values phi[27] (3D) / [9] (2D)
+// reference gradient Gr[c][r] = d u_c / d t_r of the nodal field at (ijk, t)
+// and the 1D basis values l[axis][0..2] (the nodal basis values are their
+// products)
 template <int D>
 __device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, double>::type> U, int nnx, int nny,
-                                                   const int ijk[3], const double *t, double Gr[3][3], double *phi)
+                                                   const int ijk[3], const double *t, double Gr[3][3], double l[3][3])
 {
-    double l[3][3], dl[3][3];
+    double dl[3][3];
     for (int a = 0; a < D; ++a) {
         lag3(t[a], l[a]);
         dlag3(t[a], dl[a]);
@@ -50,18 +51,15 @@ __device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, doub
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const auto v = U[base + a + (int64_t)nnx * b + sz * c3];
-                double w0, w1, w2 = 0.0, ph;
+                double w0, w1, w2 = 0.0;
                 if constexpr (D == 2) {
                     w0 = dl[0][a] * l[1][b];
                     w1 = l[0][a] * dl[1][b];
-                    ph = l[0][a] * l[1][b];
                 } else {
                     w0 = dl[0][a] * l[1][b] * l[2][c3];
                     w1 = l[0][a] * dl[1][b] * l[2][c3];
                     w2 = l[0][a] * l[1][b] * dl[2][c3];
-                    ph = l[0][a] * l[1][b] * l[2][c3];
                 }
-                phi[a + 3 * b + 9 * c3] = ph;
                 const double vc[3] = {(double)nv_x(v), (double)nv_y(v), (double)nv_z(v)};
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
@@ -175,8 +173,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
                 }
             }
             for (int st = NS - 1; st >= 0; --st) {
-                double Gr[3][3], phi[27];
-                grad_basis_uniform<D>(Ug, m.nnx, m.nny, jk[st], ty[st], Gr, phi);
+                double Gr[3][3], l[3][3];
+                grad_basis_uniform<D>(Ug, m.nnx, m.nny, jk[st], ty[st], Gr, l);
                 for (int j = 0; j < D; ++j) {
                     double acc = 0.0;
                     for (int c = 0; c < D; ++c) acc += Gr[c][j] * kb[st][c];
@@ -186,19 +184,28 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
                 const int di = jk[st][0] - b0[0] + 1, dj = jk[st][1] - b0[1] + 1, dk = jk[st][2] - b0[2] + 1;
                 bool inw = ((unsigned)di < (unsigned)(BX + 2)) & ((unsigned)dj < (unsigned)(BY + 2));
                 if constexpr (D == 3) inw &= (unsigned)dk < (unsigned)(BZ + 2);
-                for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
-                    for (int b = 0; b < 3; ++b)
-                        for (int a = 0; a < 3; ++a) {
-                            const double f = dt * phi[a + 3 * b + 9 * c3];
-                            if (inw) {
-                                const int q = (2 * di + a) + Wn::WX * ((2 * dj + b) + Wn::WY * (D == 3 ? 2 * dk + c3 : 0));
-                                for (int c = 0; c < D; ++c) atomicAdd(&s_acc[c * Wn::NODES + q], f * kb[st][c]);
-                            } else {
-                                const int64_t g = (2 * jk[st][0] + a) + (int64_t)m.nnx * ((2 * jk[st][1] + b) +
-                                                  (int64_t)m.nny * (D == 3 ? 2 * jk[st][2] + c3 : 0));
-                                for (int c = 0; c < D; ++c) unsafeAtomicAdd(&dU[c * nn + g], f * kb[st][c]);
-                            }
-                        }
+                // Lanes holding particles of one cell would add to the same
+                // node at the same time (serialised LDS atomics); each lane
+                // starts its walk over the cell's nodes at its own offset.
+                constexpr int NB = D == 3 ? 27 : 9;
+                const int rot = (threadIdx.x & 63) % NB;
+                for (int r = 0; r < NB; ++r) {
+                    const int nq = r + rot >= NB ? r + rot - NB : r + rot;
+                    const int a = nq % 3, b = (nq / 3) % 3, c3 = D == 3 ? nq / 9 : 0;
+                    const double la = a == 0 ? l[0][0] : (a == 1 ? l[0][1] : l[0][2]);
+                    const double lb = b == 0 ? l[1][0] : (b == 1 ? l[1][1] : l[1][2]);
+                    double ph = la * lb;
+                    if constexpr (D == 3) ph *= c3 == 0 ? l[2][0] : (c3 == 1 ? l[2][1] : l[2][2]);
+                    const double f = dt * ph;
+                    if (inw) {
+                        const int q = (2 * di + a) + Wn::WX * ((2 * dj + b) + Wn::WY * (D == 3 ? 2 * dk + c3 : 0));
+                        for (int c = 0; c < D; ++c) atomicAdd(&s_acc[c * Wn::NODES + q], f * kb[st][c]);
+                    } else {
+                        const int64_t g = (2 * jk[st][0] + a) + (int64_t)m.nnx * ((2 * jk[st][1] + b) +
+                                          (int64_t)m.nny * (D == 3 ? 2 * jk[st][2] + c3 : 0));
+                        for (int c = 0; c < D; ++c) unsafeAtomicAdd(&dU[c * nn + g], f * kb[st][c]);
+                    }
+                }
                 if constexpr (S == 2) {
                     if (st == 1)
                         for (int a = 0; a < D; ++a) kb[0][a] = 0.5 * yb[1][a];
