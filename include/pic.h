@@ -170,7 +170,9 @@ PIC_API pic_status pic_seed_positions(pic_ctx *ctx, const double *x, const uint3
                               int32_t prop_init, const void *prop_in);
 
 /* Cells per work item of the advect kernel (1..1024; default 64).  A work
- * item is a run of consecutive cells whose particles one workgroup advances. */
+ * item is a run of consecutive cells whose particles one workgroup advances.
+ * On octree meshes at most 64 are used (the tile's leaf nodes are staged in
+ * LDS). */
 PIC_API pic_status pic_set_tile(pic_ctx *ctx, int32_t tile_cells);
 
 /* ---- the hot path (Sec. 2.3 advection, Sec. 2.4 transport) -------------- */

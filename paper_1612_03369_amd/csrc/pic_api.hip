@@ -299,7 +299,9 @@ pic_status build_work(pic_ctx *c)
     const int64_t nc = c->mesh.n_cells;
     const int64_t cap = c->store.capacity;
     std::vector<WorkItem> w;
-    for (int64_t k = 0; k < nc; k += c->tile) w.push_back({0, (int32_t)k, (int32_t)std::min<int64_t>(nc, k + c->tile)});
+    // octree tiles hold at most OCT_TILE leaves (their nodes are staged in LDS)
+    const int64_t tile = c->mesh.kind == MESH_OCTREE ? std::min(c->tile, OCT_TILE) : c->tile;
+    for (int64_t k = 0; k < nc; k += tile) w.push_back({0, (int32_t)k, (int32_t)std::min<int64_t>(nc, k + tile)});
     std::vector<ScanItem> sc;
     for (int64_t k = 0; k < n_chunks(nc); ++k) sc.push_back({0, (int32_t)k});
     std::vector<RangeItem> rp, rc;
@@ -341,6 +343,9 @@ pic_status build_work(pic_ctx *c)
 // kernel dispatch over (dim, scheme, precision, mesh kind)
 // ---------------------------------------------------------------------------
 using AdvectFn = void (*)(const ProblemDev *, const WorkItem *, int);
+#ifndef PIC_OCT_LDS
+#define PIC_OCT_LDS 1       // octree advect with the tile's leaf nodes staged in LDS
+#endif
 
 template <int D, int S, typename T> AdvectFn advect_for_kind(int kind)
 {
@@ -348,7 +353,7 @@ template <int D, int S, typename T> AdvectFn advect_for_kind(int kind)
     case MESH_UNIFORM: return k_advect<D, S, T, MESH_UNIFORM>;
     case MESH_DISPLACED: return k_advect<D, S, T, MESH_DISPLACED>;
     default:
-        if constexpr (D == 3) return k_advect<D, S, T, MESH_OCTREE>;
+        if constexpr (D == 3) return PIC_OCT_LDS ? k_advect_oct<S, T> : k_advect<D, S, T, MESH_OCTREE>;
         return nullptr;
     }
 }

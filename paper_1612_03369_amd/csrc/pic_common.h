@@ -212,6 +212,37 @@ __device__ __forceinline__ void eval_q2(const MeshDev &m, const typename NodeVec
     }
 }
 
+// The same sum over the 27 node values of one cell held contiguously in
+// local order a + 3b + 9c (an LDS copy of an octree leaf's nodes); the
+// arithmetic matches eval_q2 on the global field.
+template <int D, typename T>
+__device__ __forceinline__ void eval_q2_local(const typename NodeVec<D, T>::type *W, const double *tr, double *u)
+{
+    static_assert(D == 3, "octree leaves are 3D");
+    T la[3], lb[3], lc[3];
+    lag3((T)tr[0], la);
+    lag3((T)tr[1], lb);
+    lag3((T)tr[2], lc);
+    T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll PIC_EVAL_UNROLL
+    for (int c = 0; c < 3; ++c) {
+        T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const auto v0 = W[3 * b + 9 * c], v1 = W[3 * b + 9 * c + 1], v2 = W[3 * b + 9 * c + 2];
+            r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
+            r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
+            r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
+        }
+        a0 = fma_t(lc[c], r0, a0);
+        a1 = fma_t(lc[c], r1, a1);
+        a2 = fma_t(lc[c], r2, a2);
+    }
+    u[0] = (double)a0;
+    u[1] = (double)a1;
+    u[2] = (double)a2;
+}
+
 // Reference gradient G[c][r] = d u_c / d xhat_r (double precision).
 template <int D, int KIND>
 __device__ __forceinline__ void eval_q2_refgrad(const MeshDev &m, const typename NodeVec<D, double>::type *__restrict__ U,

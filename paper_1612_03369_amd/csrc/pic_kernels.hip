@@ -11,13 +11,14 @@ namespace pic {
 // ===========================================================================
 // advect + locate (Sec. 2.3 and 2.4)
 // ===========================================================================
-template <int D, int S, typename T, int KIND>
-__device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename NodeVec<D, T>::type *__restrict__ U,
-                                               double dt, double *x, double *t, int32_t K, bool &near, LocStats &ls)
+// ev(K, t, u): the field at reference point t of cell K.
+template <int D, int S, int KIND, class Eval>
+__device__ __forceinline__ uint32_t advect_one_e(const MeshDev &m, Eval &&ev, double dt, double *x, double *t,
+                                                 int32_t K, bool &near, LocStats &ls)
 {
     double u[3], k1[3], y[3], ty[3];
     int32_t Ky;
-    eval_q2<D, T, KIND>(m, U, K, t, u);      // stage 1: stored (K, xhat), no location needed
+    ev(K, t, u);                             // stage 1: stored (K, xhat), no location needed
 #pragma unroll
     for (int a = 0; a < D; ++a) k1[a] = dt * u[a];
     double xn[3];
@@ -29,7 +30,7 @@ __device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename 
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
         near |= near_boundary<D>(m, y);
         if (!locate<D, KIND>(m, y, K, Ky, ty, ls)) return LOST;
-        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+        ev(Ky, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
     } else {
@@ -38,21 +39,21 @@ __device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename 
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
         near |= near_boundary<D>(m, y);
         if (!locate<D, KIND>(m, y, K, Ky, ty, ls)) return LOST;
-        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+        ev(Ky, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) k2[a] = dt * u[a];
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k2[a];
         near |= near_boundary<D>(m, y);
         if (!locate<D, KIND>(m, y, Ky, Ky, ty, ls)) return LOST;
-        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+        ev(Ky, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) k3[a] = dt * u[a];
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + k3[a];
         near |= near_boundary<D>(m, y);
         if (!locate<D, KIND>(m, y, Ky, Ky, ty, ls)) return LOST;
-        eval_q2<D, T, KIND>(m, U, Ky, ty, u);
+        ev(Ky, ty, u);
         const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
@@ -68,6 +69,14 @@ __device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename 
         t[a] = tn[a];
     }
     return (uint32_t)Kn;
+}
+
+template <int D, int S, typename T, int KIND>
+__device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename NodeVec<D, T>::type *__restrict__ U,
+                                               double dt, double *x, double *t, int32_t K, bool &near, LocStats &ls)
+{
+    auto ev = [&](int32_t Kc, const double *tc, double *uc) { eval_q2<D, T, KIND>(m, U, Kc, tc, uc); };
+    return advect_one_e<D, S, KIND>(m, ev, dt, x, t, K, near, ls);
 }
 
 // Uniform meshes: the same step with (i,j,k) carried along (no index division
@@ -223,6 +232,86 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
             flush_stats(P.scr.stats, ST_NEWTON_FAIL, ls.newton_fail, nullptr);
             flush_stats(P.scr.stats, ST_SEARCHED, ls.searched, nullptr);
         }
+        __syncthreads();
+    }
+}
+
+// Octree meshes: the 27 node values of every leaf of the tile are copied to
+// LDS once (leaves of a tile are consecutive, so their node lists are one
+// contiguous run of the cell -> node map); particles evaluate stage points in
+// the tile's leaves from LDS and elsewhere from the global field, with the
+// same arithmetic (identical rounding).
+constexpr int OCT_TILE = 64;
+#ifndef PIC_OCT_WAVES
+#define PIC_OCT_WAVES 3     // single precision, Euler/RK2: cap registers for this many waves per SIMD
+#endif
+template <int S, typename T>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && S <= 2 ? PIC_OCT_WAVES : 1))) void
+k_advect_oct(const ProblemDev *__restrict__ probs,
+                                                      const WorkItem *__restrict__ work, int n_work)
+{
+    using V = typename NodeVec<3, T>::type;
+    __shared__ V s_nodes[OCT_TILE * 27];
+    __shared__ int s_cnt[OCT_TILE];
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
+        const WorkItem wi = work[w];
+        const ProblemDev &P = probs[wi.problem];
+        const MeshDev &m = P.mesh;
+        const StoreDev cur = P.store[P.cur];
+        const int64_t cap = P.cap;
+        const double dt = P.dt;
+        const int c0 = wi.c0, nt = wi.c1 - wi.c0;     // nt <= OCT_TILE (work lists of octree meshes)
+        const int p0 = cur.cs[c0], p1 = cur.cs[wi.c1];
+        const V *U = reinterpret_cast<const V *>(sizeof(T) == 4 ? P.u32 : P.u64);
+        const int32_t *cn = m.cell_nodes + (int64_t)c0 * 27;
+        for (int q = threadIdx.x; q < nt * 27; q += BLOCK) s_nodes[q] = U[cn[q]];
+        for (int k = threadIdx.x; k < nt; k += BLOCK) s_cnt[k] = 0;
+        __syncthreads();
+        auto ev = [&](int32_t Kc, const double *tc, double *uc) {
+            if ((unsigned)(Kc - c0) < (unsigned)nt)
+                eval_q2_local<3, T>(s_nodes + (Kc - c0) * 27, tc, uc);
+            else
+                eval_q2<3, T, MESH_OCTREE>(m, U, Kc, tc, uc);
+        };
+        int st_lost = 0, st_moved = 0, st_near = 0;
+        LocStats ls = {0, 0, 0, 0};
+        for (int i = p0 + threadIdx.x; i < p1; i += BLOCK) {
+            const int32_t K = cur.cell[i];
+            double x[3], t[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                x[a] = cur.x[a * cap + i];
+                t[a] = cur.xr[a * cap + i];
+            }
+            bool near = false;
+            const uint32_t key = advect_one_e<3, S, MESH_OCTREE>(m, ev, dt, x, t, K, near, ls);
+            if (key != LOST) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    cur.x[a * cap + i] = x[a];
+                    cur.xr[a * cap + i] = t[a];
+                }
+            }
+            P.scr.key[P.cur][i] = key;
+            const bool stay = key == (uint32_t)K;
+            if (stay) atomicAdd(&s_cnt[K - c0], 1);
+            else if (key != LOST) atomicAdd(&P.scr.n_arrive[key], 1);
+            st_lost += key == LOST;
+            st_moved += (key != LOST) && !stay;
+            st_near += near;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nt; k += BLOCK) P.scr.n_stay[c0 + k] = s_cnt[k];
+        flush_stats(P.scr.stats, ST_PSTEPS, threadIdx.x == 0 ? p1 - p0 : 0, nullptr);
+        flush_stats(P.scr.stats, ST_LOST, st_lost, nullptr);
+        flush_stats(P.scr.stats, ST_MOVED, st_moved, nullptr);
+        flush_stats(P.scr.stats, ST_NEAR, st_near, nullptr);
+        flush_stats(P.scr.stats, ST_FIRST_TRY, ls.first_try, nullptr);
+        flush_stats(P.scr.stats, ST_FALLBACK, ls.fallback, nullptr);
+        flush_stats(P.scr.stats, ST_NEWTON_FAIL, ls.newton_fail, nullptr);
+        flush_stats(P.scr.stats, ST_SEARCHED, ls.searched, nullptr);
         __syncthreads();
     }
 }
