@@ -230,16 +230,19 @@ def test_fp32_evaluation_against_fp64_oracle(L):
     p.close()
 
 
-@pytest.mark.parametrize("dim,scheme,prec", [(3, 4, 1), (3, 2, 0), (2, 4, 0), (2, 2, 1)])
-def test_fused_steps_bit_identical_to_single_steps(L, dim, scheme, prec):
-    """advance(n) fuses each re-sort with the next advect; the result must equal n
-    separate one-step advances bit for bit (store, order, counters)."""
-    _say(f"case: fused vs single steps dim={dim} scheme={scheme} prec={prec}")
-    n = 20 if dim == 2 else 11
+@pytest.mark.parametrize("dim,scheme,prec,dense", [(3, 4, 1, 0), (3, 2, 0, 0), (2, 4, 0, 0), (2, 2, 1, 0),
+                                                   (3, 4, 1, 40), (3, 4, 0, 40), (3, 2, 1, 110), (2, 4, 1, 80)])
+def test_fused_steps_bit_identical_to_single_steps(L, dim, scheme, prec, dense):
+    """advance(n) fuses each re-sort with the next advect; the result must equal n separate
+    one-step advances bit for bit (store, order, counters).  `dense` sets the particles per
+    cell of the crowded cases (thousands of particles per cell block)."""
+    _say(f"case: fused vs single steps dim={dim} scheme={scheme} prec={prec} dense={dense}")
+    n = (20 if dim == 2 else 11) if not dense else (16 if dim == 2 else 8)
     mesh = I.UniformMesh(dim, (n,) * dim)
     f = I.FourierField(dim, seed=900 + dim)
     U = I.normalise_nodal(I.sample_nodes(f.velocity, I.uniform_q2_nodes(mesh)))
-    counts = np.random.default_rng(901).integers(0, 15, mesh.n_cells).astype(np.int32)
+    hi = 15 if not dense else 2 * dense
+    counts = np.random.default_rng(901).integers(0 if not dense else dense // 2, hi, mesh.n_cells).astype(np.int32)
     counts, xr, ids = I.draw_reference_particles(counts, dim, seed=902)
     cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=2,
                prop_dtype=np.float32 if prec else np.float64)
