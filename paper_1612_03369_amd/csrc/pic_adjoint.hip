@@ -31,9 +31,11 @@ template <int D, int BX, int BY, int BZ> struct NodeWin {
 // reference gradient Gr[c][r] = d u_c / d t_r of the nodal field at (ijk, t)
 // and the 1D basis values l[axis][0..2] (the nodal basis values are their
 // products)
-template <int D>
-__device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, double>::type> U, int nnx, int nny,
-                                                   const int ijk[3], const double *t, double Gr[3][3], double l[3][3])
+// base = index of local node (0,0,0) of the cell in the grid U, sy / sz = the
+// grid's row strides (global node array or the block's LDS window)
+template <int D, typename Ptr, typename I>
+__device__ __forceinline__ void grad_basis_at(Ptr U, I base, I sy, I sz, const double *t, double Gr[3][3],
+                                              double l[3][3])
 {
     double dl[3][3];
     for (int a = 0; a < D; ++a) {
@@ -42,15 +44,13 @@ __device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, doub
     }
     for (int c = 0; c < 3; ++c)
         for (int r = 0; r < 3; ++r) Gr[c][r] = 0.0;
-    const int64_t sz = (int64_t)nnx * nny;
-    const int64_t base = 2 * ijk[0] + (int64_t)nnx * (2 * ijk[1]) + (D == 3 ? sz * (2 * ijk[2]) : 0);
-#pragma unroll
+#pragma unroll 1
     for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const auto v = U[base + a + (int64_t)nnx * b + sz * c3];
+                const auto v = U[base + a + sy * b + sz * c3];
                 double w0, w1, w2 = 0.0;
                 if constexpr (D == 2) {
                     w0 = dl[0][a] * l[1][b];
@@ -79,7 +79,7 @@ __device__ __forceinline__ void grad_basis_uniform(gptr<typename NodeVec<D, doub
  * block are summed in LDS before one atomic per window node.
  */
 template <int D, int S, int BX, int BY, int BZ>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restrict__ probs,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_blk(const ProblemDev *__restrict__ probs,
                                                        const BlockItem *__restrict__ work, int n_work,
                                                        const double *__restrict__ x_in, const double *__restrict__ xr_in,
                                                        const int32_t *__restrict__ cell_in, const int32_t *__restrict__ cs_in,
@@ -89,6 +89,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
     using Wn = NodeWin<D, BX, BY, BZ>;
     using V = typename NodeVec<D, double>::type;
     __shared__ double s_acc[Wn::NODES * D];
+    __shared__ V s_u[Wn::NODES];                  // the field on the same window
     __shared__ int s_pre[Wn::ROWS + 1];
     __shared__ int s_beg[Wn::ROWS];
     const ProblemDev &P = probs[0];
@@ -105,6 +106,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
         const int nx = min(BX, m.n[0] - bi.i0), ny = min(BY, m.n[1] - bi.j0);
         const int nz = D == 3 ? min(BZ, m.n[2] - bi.k0) : 1;
         for (int q = threadIdx.x; q < Wn::NODES * D; q += BLOCK) s_acc[q] = 0.0;
+        for (int q = threadIdx.x; q < Wn::NODES; q += BLOCK) {
+            const int wx = q % Wn::WX, wy = (q / Wn::WX) % Wn::WY, wz = q / (Wn::WX * Wn::WY);
+            const int gx = 2 * b0[0] - 2 + wx, gy = 2 * b0[1] - 2 + wy, gz = D == 3 ? 2 * b0[2] - 2 + wz : 0;
+            if (gx >= 0 && gx < m.nnx && gy >= 0 && gy < m.nny && gz >= 0 && gz < m.nnz)
+                s_u[q] = Ug[gx + (int64_t)m.nnx * (gy + (int64_t)m.nny * gz)];
+        }
         if (threadIdx.x < 64) {
             const int r = threadIdx.x;
             int len = 0, beg = 0;
@@ -147,14 +154,30 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
                 ty[0][a] = xr_in[a * cap + i];
             }
             ijk_of<D>(m, (uint32_t)cell_in[i], jk[0]);
+            // window node index of local node (0,0,0) of cell ijk, or -1 outside the window
+            auto wbase = [&](const int *ijk) {
+                const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;
+                bool inw = ((unsigned)di < (unsigned)(BX + 2)) & ((unsigned)dj < (unsigned)(BY + 2));
+                if constexpr (D == 3) inw &= (unsigned)dk < (unsigned)(BZ + 2);
+                return inw ? 2 * di + Wn::WX * (2 * dj + (D == 3 ? Wn::WY * 2 * dk : 0)) : -1;
+            };
+            const int64_t gsz = (int64_t)m.nnx * m.nny;
+            auto gbase = [&](const int *ijk) {
+                return 2 * ijk[0] + (int64_t)m.nnx * (2 * ijk[1]) + (D == 3 ? gsz * (2 * ijk[2]) : 0);
+            };
             constexpr int NS = S == 4 ? 4 : S;
+#pragma unroll
             for (int st = 0; st < NS; ++st) {
                 if (st > 0) {
                     const double fct = (S == 4 && st == 3) ? 1.0 : 0.5;
                     for (int a = 0; a < D; ++a) y[a] = x[a] + fct * k[st - 1][a];
                     locate_stage<D>(m, y, jk[st], ty[st], near);
                 }
-                eval_q2_ijk<D, double>(Ug, m.nnx, m.nny, jk[st], ty[st], u);
+                const int wq = wbase(jk[st]);
+                if (wq >= 0)
+                    eval_q2_at<D, double>((const V *)s_u, wq, (int)Wn::WX, (int)(Wn::WX * Wn::WY), ty[st], u);
+                else
+                    eval_q2_at<D, double>(Ug, gbase(jk[st]), (int64_t)m.nnx, gsz, ty[st], u);
                 for (int a = 0; a < D; ++a) k[st][a] = dt * u[a];
             }
             double lam[3], kb[4][3], yb[4][3];
@@ -172,9 +195,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_blk(const ProblemDev *__restr
                     kb[3][a] = lam[a] / 6.0;
                 }
             }
+#pragma unroll
             for (int st = NS - 1; st >= 0; --st) {
                 double Gr[3][3], l[3][3];
-                grad_basis_uniform<D>(Ug, m.nnx, m.nny, jk[st], ty[st], Gr, l);
+                const int wq = wbase(jk[st]);
+                if (wq >= 0)
+                    grad_basis_at<D>((const V *)s_u, wq, (int)Wn::WX, (int)(Wn::WX * Wn::WY), ty[st], Gr, l);
+                else
+                    grad_basis_at<D>(Ug, gbase(jk[st]), (int64_t)m.nnx, gsz, ty[st], Gr, l);
                 for (int j = 0; j < D; ++j) {
                     double acc = 0.0;
                     for (int c = 0; c < D; ++c) acc += Gr[c][j] * kb[st][c];

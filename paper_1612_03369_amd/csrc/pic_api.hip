@@ -63,6 +63,8 @@ struct pic_ctx {
     int n_rc = 0;
     BlockItem *d_blk[2] = {nullptr, nullptr};   // uniform meshes: cell blocks for F64 / F32 evaluation
     int n_blk[2] = {0, 0};
+    BlockItem *d_blk_adj = nullptr;             // uniform meshes: cell blocks of the reverse (adjoint) step
+    int n_blk_adj = 0;
     double last_dt = std::nan("");
     // profiling
     bool profile = false;
@@ -256,6 +258,11 @@ pic_status upload_problem(pic_ctx *c)
 constexpr int BLK3_F32[3] = {PIC_BLK3_F32};
 constexpr int BLK3_F64[3] = {4, 4, 4};
 constexpr int BLK2[3] = {8, 8, 1};
+// Cell blocks of the reverse step: smaller in 3D, so that its two LDS windows
+// (field and dU accumulators, double precision) leave room for two workgroups
+// per CU.
+constexpr int ADJ3[3] = {4, 2, 2};
+constexpr int ADJ2[3] = {8, 8, 1};
 inline const int *block_shape(int dim, int prec)
 {
     return dim == 2 ? BLK2 : (prec == PIC_F32 ? BLK3_F32 : BLK3_F64);
@@ -331,6 +338,15 @@ pic_status build_work(pic_ctx *c)
         if ((s = dalloc(c, &c->d_blk[pr], bl.size()))) return s;
         HIPCHK(c, hipMemcpy(c->d_blk[pr], bl.data(), bl.size() * sizeof(BlockItem), hipMemcpyHostToDevice));
         c->n_blk[pr] = (int)bl.size();
+    }
+    if (c->d_blk_adj) hipFree(c->d_blk_adj);
+    c->d_blk_adj = nullptr;
+    c->n_blk_adj = 0;
+    if (c->mesh.kind == MESH_UNIFORM) {
+        std::vector<BlockItem> bl = block_items_shape(c->mesh, c->mesh.dim == 3 ? ADJ3 : ADJ2, 0);
+        if ((s = dalloc(c, &c->d_blk_adj, bl.size()))) return s;
+        HIPCHK(c, hipMemcpy(c->d_blk_adj, bl.data(), bl.size() * sizeof(BlockItem), hipMemcpyHostToDevice));
+        c->n_blk_adj = (int)bl.size();
     }
     c->n_work = (int)w.size();
     c->n_scan = (int)sc.size();
@@ -539,7 +555,7 @@ extern "C" void pic_destroy(pic_ctx *c)
     else hipDeviceSynchronize();
     free_mesh(c);
     for (void *p : {c->u64, c->u32, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
-                    (void *)c->d_rc, (void *)c->d_blk[0], (void *)c->d_blk[1]})
+                    (void *)c->d_rc, (void *)c->d_blk[0], (void *)c->d_blk[1], (void *)c->d_blk_adj})
         if (p) hipFree(p);
     for (auto &p : c->pending) {
         hipEventDestroy(p.a);
