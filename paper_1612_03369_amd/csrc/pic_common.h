@@ -285,8 +285,10 @@ __device__ __forceinline__ void eval_q2_refgrad(const MeshDev &m, const typename
 // pass of the compiler sees a plain pointer
 #if defined(__HIP_DEVICE_COMPILE__)
 template <typename V> using gptr = const V __attribute__((address_space(1))) *;
+template <typename V> using gptr_mut = V __attribute__((address_space(1))) *;
 #else
 template <typename V> using gptr = const V *;
+template <typename V> using gptr_mut = V *;
 #endif
 
 // (i,j,k) of cell K with 32-bit arithmetic (cells < 2^31)

@@ -850,10 +850,15 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 }
 
 // Sort each cell's arrivals by their previous position (= previous global
-// order, since the previous store was sorted by cell).
+// order, since the previous store was sorted by cell); one thread per cell.
+// Up to FIX_LDS arrivals are sorted in LDS (thread t's list interleaved with
+// the others' so that the threads of a wave hit distinct banks); longer lists
+// (rare) in place in global memory.
+constexpr int FIX_LDS = 32;
 __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                int n_items)
 {
+    __shared__ int32_t s_v[FIX_LDS * BLOCK];
     for (int wb = blockIdx.x; wb < xcd_span(n_items); wb += gridDim.x) {
         const int w = xcd_item(wb, n_items);
         if (w >= n_items) continue;
@@ -864,26 +869,28 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
         const StoreDev nxt = P.store[1 - P.cur];
         const int64_t b = (int64_t)nxt.cs[K] + P.scr.n_stay[K];
         const int64_t e = nxt.cs[K + 1];
-        if (e - b < 2) continue;
-        int32_t *a = P.scr.src + b;
-        const int64_t n = e - b;
-        if (n <= 32) {
-            int32_t v[32];
-            for (int64_t q = 0; q < n; ++q) v[q] = a[q];
-            for (int64_t q = 1; q < n; ++q) {
-                int32_t x = v[q];
-                int64_t r = q - 1;
-                while (r >= 0 && v[r] > x) {
-                    v[r + 1] = v[r];
+        const int n = (int)(e - b);
+        if (n < 2) continue;
+        auto a = (gptr_mut<int32_t>)(P.scr.src + b);
+        if (n <= FIX_LDS) {
+            int32_t *v = s_v + threadIdx.x;
+#pragma unroll
+            for (int q = 0; q < FIX_LDS; ++q)
+                if (q < n) v[q * BLOCK] = a[q];
+            for (int q = 1; q < n; ++q) {
+                const int32_t x = v[q * BLOCK];
+                int r = q - 1;
+                while (r >= 0 && v[r * BLOCK] > x) {
+                    v[(r + 1) * BLOCK] = v[r * BLOCK];
                     --r;
                 }
-                v[r + 1] = x;
+                v[(r + 1) * BLOCK] = x;
             }
-            for (int64_t q = 0; q < n; ++q) a[q] = v[q];
+            for (int q = 0; q < n; ++q) a[q] = v[q * BLOCK];
         } else {
-            for (int64_t q = 1; q < n; ++q) {         // rare: many arrivals in one cell
-                int32_t x = a[q];
-                int64_t r = q - 1;
+            for (int q = 1; q < n; ++q) {         // rare: many arrivals in one cell
+                const int32_t x = a[q];
+                int r = q - 1;
                 while (r >= 0 && a[r] > x) {
                     a[r + 1] = a[r];
                     --r;
