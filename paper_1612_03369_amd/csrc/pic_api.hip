@@ -211,13 +211,13 @@ size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)
     char *nid = take(8 * (size_t)(1 + STAT_STRIPES));
     char *fl = take(16);
     if (s) {
-        s->key[0] = (uint32_t *)key0;
-        s->key[1] = (uint32_t *)key1;
-        s->src = (int32_t *)src;
-        s->n_stay = (int32_t *)stay;
-        s->n_arrive = (int32_t *)arr;
-        s->cursor = (int32_t *)cur;
-        s->chunk = (int64_t *)chk;
+        s->key[0] = (uint32_t PIC_G *)key0;
+        s->key[1] = (uint32_t PIC_G *)key1;
+        s->src = (int32_t PIC_G *)src;
+        s->n_stay = (int32_t PIC_G *)stay;
+        s->n_arrive = (int32_t PIC_G *)arr;
+        s->cursor = (int32_t PIC_G *)cur;
+        s->chunk = (int64_t PIC_G *)chk;
         s->stats = (unsigned long long *)st;
         s->next_id = (unsigned long long *)nid;
         s->flags = (int32_t *)fl;
@@ -765,7 +765,9 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     ProblemDev &P = c->h_prob;
     P = ProblemDev{};
     P.mesh = c->mesh;
-    for (int b = 0; b < 2; ++b) P.store[b] = StoreDev{s->x[b], s->xr[b], s->cell[b], s->id[b], s->prop[b], s->cell_start[b]};
+    for (int b = 0; b < 2; ++b)
+        P.store[b] = make_store((double *)s->x[b], (double *)s->xr[b], (int32_t *)s->cell[b], (uint32_t *)s->id[b],
+                                s->prop[b], (int32_t *)s->cell_start[b]);
     P.cur = 0;
     P.n_prop = s->n_prop;
     P.prop_f64 = s->prop_prec == PIC_F64;

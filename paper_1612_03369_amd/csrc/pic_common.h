@@ -53,24 +53,45 @@ struct MeshDev {
     const int32_t *nbr;       // [nbr_off[n_cells]]
 };
 
+// Pointers into device memory that kernels read from structures: in device
+// code they carry the global address space, so that their loads and stores
+// are global (not flat) accesses, which do not hold up waits on LDS.
+#ifdef __HIP_DEVICE_COMPILE__
+#define PIC_G __attribute__((address_space(1)))
+#else
+#define PIC_G
+#endif
+
 // One buffer of the particle store.
 struct StoreDev {
-    double *x;       // [dim][cap]
-    double *xr;      // [dim][cap]
-    int32_t *cell;   // [cap]
-    uint32_t *id;    // [cap]
-    void *prop;      // [n_prop][cap]
-    int32_t *cs;     // [n_cells + 1]
+    double PIC_G *x;       // [dim][cap]
+    double PIC_G *xr;      // [dim][cap]
+    int32_t PIC_G *cell;   // [cap]
+    uint32_t PIC_G *id;    // [cap]
+    void PIC_G *prop;      // [n_prop][cap]
+    int32_t PIC_G *cs;     // [n_cells + 1]
 };
+
+inline StoreDev make_store(double *x, double *xr, int32_t *cell, uint32_t *id, void *prop, int32_t *cs)
+{
+    StoreDev s;
+    s.x = (double PIC_G *)x;
+    s.xr = (double PIC_G *)xr;
+    s.cell = (int32_t PIC_G *)cell;
+    s.id = (uint32_t PIC_G *)id;
+    s.prop = (void PIC_G *)prop;
+    s.cs = (int32_t PIC_G *)cs;
+    return s;
+}
 
 // Per-context scratch (carved out of the caller's workspace).
 struct ScratchDev {
-    uint32_t *key[2];     // [cap] per buffer: new cell (or LOST) of the particle at that position
-    int32_t *src;         // [cap] gather source of each destination slot
-    int32_t *n_stay;      // [nc]
-    int32_t *n_arrive;    // [nc]
-    int32_t *cursor;      // [nc]
-    int64_t *chunk;       // [n_chunks + 1]
+    uint32_t PIC_G *key[2];     // [cap] per buffer: new cell (or LOST) of the particle at that position
+    int32_t PIC_G *src;         // [cap] gather source of each destination slot
+    int32_t PIC_G *n_stay;      // [nc]
+    int32_t PIC_G *n_arrive;    // [nc]
+    int32_t PIC_G *cursor;      // [nc]
+    int64_t PIC_G *chunk;       // [n_chunks + 1]
     unsigned long long *stats;  // [STAT_STRIPES][ST_COUNT]
     unsigned long long *next_id;// [1 + STAT_STRIPES]: next_id[0], then striped maxima written by seeding
     int32_t *flags;       // [4]
