@@ -72,6 +72,8 @@ def lib():
             L.orc_seed.restype = C.c_int
             L.orc_seed.argtypes = [P, P, P, C.c_int64, P, C.c_int, P]
             L.orc_advect.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, P, P, P]
+            L.orc_advect_odes.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
+                                          C.c_int, C.c_int, P, P, P]
             L.orc_sort_perm.restype = C.c_int64
             L.orc_sort_perm.argtypes = [C.c_int64, C.c_int64, P, P, P, P]
             L.orc_step.restype = C.c_int
@@ -343,6 +345,17 @@ def advect(mesh: OracleMesh, U, dt, scheme, st: OracleStore):
     near = np.zeros(max(st.n, 1), np.uint8)
     lib().orc_advect(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), C.byref(st.c),
                      _p(key), _p(near))
+    return key[: st.n], near[: st.n]
+
+
+def advect_odes(mesh: OracleMesh, U, dt, scheme, st: OracleStore, alpha, beta, damage_prop, deform_prop):
+    """Advection + location with the damage and deformation-gradient equations of Sec. 2.6 integrated
+    by the same RK scheme (no reordering); returns (key, near)."""
+    U = np.ascontiguousarray(U, np.float64)
+    key = np.zeros(max(st.n, 1), np.uint32)
+    near = np.zeros(max(st.n, 1), np.uint8)
+    lib().orc_advect_odes(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), float(alpha), float(beta),
+                          int(damage_prop), int(deform_prop), C.byref(st.c), _p(key), _p(near))
     return key[: st.n], near[: st.n]
 
 

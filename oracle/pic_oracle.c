@@ -582,6 +582,124 @@ void orc_advect(const orc_mesh *m, const double *U, int64_t nn, double dt, int s
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* property equations integrated along the trajectory (Sec. 2.6)        */
+/* ------------------------------------------------------------------ */
+/*
+ * Right-hand sides of the two property equations of Sec. 2.6 at one point
+ * with velocity gradient G[i][j] = d u_i / d x_j:
+ *   damage       d' = alpha |eps| - beta d,  eps = (G + G^T) / 2,
+ *                |eps| the Frobenius norm sqrt(sum_ij eps_ij^2);
+ *   deformation  F' = G F  (F row-major, dim x dim).
+ */
+static void prop_rhs(int dim, const double G[3][3], double alpha, double beta, double dmg, const double *F,
+                     double *ddmg, double *dF)
+{
+    double e2 = 0.0;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double e = 0.5 * (G[i][j] + G[j][i]);
+            e2 += e * e;
+        }
+    *ddmg = alpha * sqrt(e2) - beta * dmg;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < dim; ++k) acc += G[i][k] * F[k * dim + j];
+            dF[i * dim + j] = acc;
+        }
+}
+
+/*
+ * One step of the coupled system (x, d, F) with the explicit RK scheme of
+ * the positions: every stage evaluates u and grad u at the stage point (in
+ * the cell the point was located in) and the property right-hand sides at
+ * the stage's property values.  Stage 1 uses the stored (K, xhat).
+ * P = [d, F_00, F_01, ...] (1 + dim^2 values).
+ */
+static int advect_one_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme, double alpha,
+                           double beta, const double *x, int32_t K, const double *xr, const double *P,
+                           double *xn, int32_t *Kn, double *xrn, double *Pn, int *near)
+{
+    int d = m->dim, np = 1 + d * d;
+    int ns = scheme == 1 ? 1 : (scheme == 2 ? 2 : 4);
+    double kx[4][3], kP[4][10], y[3], Ps[10], u[3], G[3][3], yr[3];
+    int32_t Ky;
+    *near = 0;
+    for (int s = 0; s < ns; ++s) {
+        if (s == 0) {
+            orc_eval(m, U, nn, K, xr, u);
+            eval_grad(m, U, nn, K, xr, G);
+            for (int q = 0; q < np; ++q) Ps[q] = P[q];
+        } else {
+            /* RK2: midpoint; RK4: x + k1/2, x + k2/2, x + k3 */
+            double c = (scheme == 4 && s == 3) ? 1.0 : 0.5;
+            for (int a = 0; a < d; ++a) y[a] = x[a] + c * kx[s - 1][a];
+            for (int q = 0; q < np; ++q) Ps[q] = P[q] + c * kP[s - 1][q];
+            if (near_boundary(m, y)) *near = 1;
+            if (!velocity_at(m, U, nn, y, u, &Ky, yr)) return 0;
+            eval_grad(m, U, nn, Ky, yr, G);
+        }
+        double dd, dF[9];
+        prop_rhs(d, G, alpha, beta, Ps[0], Ps + 1, &dd, dF);
+        for (int a = 0; a < d; ++a) kx[s][a] = dt * u[a];
+        kP[s][0] = dt * dd;
+        for (int q = 0; q < d * d; ++q) kP[s][1 + q] = dt * dF[q];
+    }
+    if (scheme == 1) {
+        for (int a = 0; a < d; ++a) xn[a] = x[a] + kx[0][a];
+        for (int q = 0; q < np; ++q) Pn[q] = P[q] + kP[0][q];
+    } else if (scheme == 2) {
+        for (int a = 0; a < d; ++a) xn[a] = x[a] + kx[1][a];
+        for (int q = 0; q < np; ++q) Pn[q] = P[q] + kP[1][q];
+    } else {
+        for (int a = 0; a < d; ++a) xn[a] = x[a] + kx[0][a] / 6.0 + kx[1][a] / 3.0 + kx[2][a] / 3.0 + kx[3][a] / 6.0;
+        for (int q = 0; q < np; ++q) Pn[q] = P[q] + kP[0][q] / 6.0 + kP[1][q] / 3.0 + kP[2][q] / 3.0 + kP[3][q] / 6.0;
+    }
+    if (near_boundary(m, xn)) *near = 1;
+    if (!orc_locate(m, xn, Kn, xrn)) return 0;
+    if (face_distance(d, xrn) < NEAR_FACE_TOL) *near = 1;
+    return 1;
+}
+
+/*
+ * orc_advect with the property equations: damage in property damage_prop,
+ * the deformation gradient in properties deform_prop .. deform_prop + dim^2 - 1
+ * (row-major).  Both must be given (>= 0).
+ */
+void orc_advect_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme, double alpha, double beta,
+                     int damage_prop, int deform_prop, orc_store *s, uint32_t *key, uint8_t *near)
+{
+    int d = m->dim, np = 1 + d * d;
+    int64_t cap = s->cap;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < s->n; ++i) {
+        double x[3], t[3], xn[3], tn[3], P[10], Pn[10];
+        int32_t Kn;
+        int nf;
+        for (int a = 0; a < d; ++a) {
+            x[a] = s->x[a * cap + i];
+            t[a] = s->xr[a * cap + i];
+        }
+        P[0] = s->prop[damage_prop * cap + i];
+        for (int q = 0; q < d * d; ++q) P[1 + q] = s->prop[(deform_prop + q) * cap + i];
+        int alive = advect_one_odes(m, U, nn, dt, scheme, alpha, beta, x, s->cell[i], t, P, xn, &Kn, tn, Pn, &nf);
+        near[i] = (uint8_t)nf;
+        if (!alive) {
+            key[i] = ORC_LOST;
+            continue;
+        }
+        for (int a = 0; a < d; ++a) {
+            s->x[a * cap + i] = xn[a];
+            s->xr[a * cap + i] = tn[a];
+        }
+        s->prop[damage_prop * cap + i] = Pn[0];
+        for (int q = 0; q < d * d; ++q) s->prop[(deform_prop + q) * cap + i] = Pn[1 + q];
+        (void)np;
+        key[i] = (uint32_t)Kn;
+    }
+}
+
 /*
  * Stable counting sort of the surviving particles by (new cell, moved).
  * perm[j] = pre-step index of the particle that lands at position j.

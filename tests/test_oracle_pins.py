@@ -643,3 +643,67 @@ def test_rk4_second_stage_outside_loses_particle():
     assert only2.sum() > 50
     alive = ins(y2) & ins(y3) & ins(y4) & ins(xe)
     assert got == set(v0["id"][alive].tolist())
+
+
+# ----------------------------------------------------------------------------
+# property equations of Sec. 2.6 integrated along the trajectories
+# ----------------------------------------------------------------------------
+def _rk_polynomial(Z, scheme):
+    """Stability polynomial R(Z) of the explicit scheme (the exact one-step map of y' = A y)."""
+    eye = np.eye(Z.shape[0]) if Z.ndim == 2 else 1.0
+    terms = {1: 1, 2: 2, 4: 4}[scheme]
+    out, p = eye, eye
+    for k in range(1, terms + 1):
+        p = p @ Z / k if Z.ndim == 2 else p * Z / k
+        out = out + p
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("scheme", [1, 2, 4])
+def test_property_odes_linear_field_closed_forms(dim, scheme):
+    """Under a linear field u = A (x - c) (exact in Q2) grad u = A everywhere, so one step maps
+    F to R(A dt) F and the damage error e = d - d* (d* = alpha |sym A|_F / beta) to R(-beta dt) e,
+    with R the scheme's stability polynomial.  A is not symmetric and F0 is not the identity, so a
+    transposed gradient or F G instead of G F fails; the damage recursion checks that every stage
+    sees its own stage value of d."""
+    rng = np.random.default_rng(2600 + dim)
+    n = 8
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    om = O.OracleMesh.uniform(mesh)
+    A = rng.uniform(-1.0, 1.0, (dim, dim))
+    c = np.full(dim, 0.5)
+    nodes = I.uniform_q2_nodes(mesh)
+    U = A @ (nodes - c[:, None])
+    counts = np.zeros(mesh.n_cells, np.int32)
+    centre = sum((n // 2) * n ** a for a in range(dim))
+    counts[centre] = 6
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=2610 + dim)
+    npr = 1 + dim * dim
+    st = O.seed(om, counts, xr, ids, npr)
+    m = st.n
+    d0 = 0.3
+    F0 = rng.uniform(-1.0, 1.0, (dim, dim)) + 2.0 * np.eye(dim)
+    st.prop[0, :m] = d0
+    st.prop[1:npr, :m] = F0.reshape(-1)[:, None]
+    x0 = st.x[:, :m].copy()
+    alpha, beta, dt, steps = 0.7, 1.3, 0.01, 7
+    for _ in range(steps):
+        key, _ = O.advect_odes(om, U, dt, scheme, st, alpha, beta, 0, 1)
+        assert np.all(key != O.LOST)
+        st.cell[:m] = key.astype(np.int32)
+    R = _rk_polynomial(A * dt, scheme)
+    Rn = np.linalg.matrix_power(R, steps)
+    F_exp = Rn @ F0
+    x_exp = c[:, None] + Rn @ (x0 - c[:, None])
+    S = 0.5 * (A + A.T)
+    dstar = alpha * np.sqrt((S * S).sum()) / beta
+    r = _rk_polynomial(np.float64(-beta * dt), scheme)
+    d_exp = dstar + r ** steps * (d0 - dstar)
+    assert np.abs(st.x[:, :m] - x_exp).max() < 1e-13
+    assert np.abs(st.prop[0, :m] - d_exp).max() < 1e-13
+    F = st.prop[1:npr, :m].T.reshape(m, dim, dim)
+    assert np.abs(F - F_exp[None]).max() < 1e-12
+    # the wrong product order or a transposed gradient would give these instead
+    assert np.abs(F0 @ Rn - F_exp).max() > 1e-6
+    assert np.abs(np.linalg.matrix_power(_rk_polynomial(A.T * dt, scheme), steps) @ F0 - F_exp).max() > 1e-6
