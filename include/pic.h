@@ -175,6 +175,21 @@ PIC_API pic_status pic_seed_positions(pic_ctx *ctx, const double *x, const uint3
  * LDS). */
 PIC_API pic_status pic_set_tile(pic_ctx *ctx, int32_t tile_cells);
 
+/* ---- properties integrated along the trajectories (Sec. 2.6) ----------- */
+/* Switch on the two property equations of Sec. 2.6 for pic_advance:
+ *   damage       d' = alpha |eps(u)| - beta d, eps = (grad u + grad u^T)/2,
+ *                |.| the Frobenius norm, in property damage_prop;
+ *   deformation  F' = (grad u) F, F row-major dim x dim, in properties
+ *                deform_prop .. deform_prop + dim^2 - 1.
+ * They are integrated with the positions as one system by the same RK
+ * scheme: every stage evaluates grad u_h in the cell its point was located
+ * in, at the stage's property values.  Needs double-precision properties
+ * (PIC_EINVAL otherwise, or for indices out of range / overlapping).
+ * damage_prop = deform_prop = -1 switches them off; pic_bind_store also does.
+ * Not available in batches (pic_batch_create returns PIC_EINVAL). */
+PIC_API pic_status pic_set_property_odes(pic_ctx *ctx, int32_t damage_prop, int32_t deform_prop, double alpha,
+                                         double beta);
+
 /* ---- the hot path (Sec. 2.3 advection, Sec. 2.4 transport) -------------- */
 /* n_steps time steps of size dt: per step every particle is advanced with the
  * scheme (Euler; RK2 explicit midpoint; classical RK4), every stage point and

@@ -28,7 +28,8 @@ EXPORTS = [
     "pic_create", "pic_set_stream", "pic_destroy", "pic_last_error",
     "pic_mesh_uniform", "pic_mesh_displace", "pic_mesh_octree", "pic_mesh_info", "pic_q2_nodes",
     "pic_set_velocity", "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
-    "pic_seed_reference", "pic_seed_positions", "pic_advance", "pic_population", "pic_interpolate",
+    "pic_seed_reference", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
+    "pic_interpolate",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
     "pic_batch_create", "pic_batch_advance", "pic_batch_set_schedule", "pic_batch_tune", "pic_batch_destroy",
@@ -91,6 +92,7 @@ def load(path: str | None = None):
             "pic_seed_reference": (S, [P, P, P, P, I64, I32, P]),
             "pic_seed_positions": (S, [P, P, P, I64, I32, P]),
             "pic_advance": (S, [P, D, I32, I32, I32]),
+            "pic_set_property_odes": (S, [P, I32, I32, C.c_double, C.c_double]),
             "pic_population": (S, [P, I32, I32, U64, U64]),
             "pic_interpolate": (S, [P, I32, P, P, P]),
             "pic_adjoint_workspace_bytes": (S, [P, I32, I32, P]),

@@ -217,6 +217,12 @@ class Problem:
     def advance(self, dt, n_steps=1, scheme=L.PIC_RK4, eval_prec=L.PIC_F64):
         self._chk(self.lib.pic_advance(self.h, float(dt), int(n_steps), int(scheme), int(eval_prec)))
 
+    def set_property_odes(self, damage_prop=-1, deform_prop=-1, alpha=0.0, beta=0.0):
+        """Integrate the damage (property damage_prop) and deformation-gradient (properties
+        deform_prop .. + dim^2 - 1, row-major) equations with the positions; -1, -1 switches off."""
+        self._chk(self.lib.pic_set_property_odes(self.h, int(damage_prop), int(deform_prop), float(alpha),
+                                                 float(beta)))
+
     def population(self, pmin, pmax, seed, step):
         self._chk(self.lib.pic_population(self.h, int(pmin), int(pmax), int(seed), int(step)))
 

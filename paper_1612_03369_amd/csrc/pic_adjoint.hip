@@ -283,32 +283,6 @@ __global__ void k_invert_scatter(const int32_t *__restrict__ src, const int32_t 
     if (p < cap && p < cs_out[nc]) dst[src[p]] = (int32_t)p;
 }
 
-// physical gradient G[c][j] = d u_c / d x_j at (K, t)
-template <int D, int KIND>
-__device__ __forceinline__ void grad_phys(const MeshDev &m, const typename NodeVec<D, double>::type *U, int64_t K,
-                                          const double *t, double G[3][3])
-{
-    double Gr[3][3];
-    eval_q2_refgrad<D, KIND>(m, U, K, t, Gr);
-    if constexpr (KIND == MESH_DISPLACED) {
-        double J[3][3];
-        map_jacobian<D, KIND>(m, K, t, J);
-        // G = Gr J^{-1}: row c solves J^T g = Gr[c]
-        double JT[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) JT[a][b] = J[b][a];
-        for (int c = 0; c < D; ++c) {
-            double s[3];
-            solve_small<D>(JT, Gr[c], s);
-            for (int j = 0; j < D; ++j) G[c][j] = s[j];
-        }
-    } else {
-        double x0[3], h[3];
-        cell_box<KIND>(m, K, x0, h);
-        for (int c = 0; c < D; ++c)
-            for (int j = 0; j < D; ++j) G[c][j] = Gr[c][j] / h[j];
-    }
-}
 
 // dU_c[node_i(K)] += w phi_i(t) kb_c with hardware FP64 atomics
 template <int D, int KIND>

@@ -363,32 +363,36 @@ using AdvectFn = void (*)(const ProblemDev *, const WorkItem *, int);
 #define PIC_OCT_LDS 1       // octree advect with the tile's leaf nodes staged in LDS
 #endif
 
-template <int D, int S, typename T> AdvectFn advect_for_kind(int kind)
+template <int D, int S, typename T, bool O> AdvectFn advect_for_kind(int kind)
 {
     switch (kind) {
-    case MESH_UNIFORM: return k_advect<D, S, T, MESH_UNIFORM>;
-    case MESH_DISPLACED: return k_advect<D, S, T, MESH_DISPLACED>;
+    case MESH_UNIFORM: return k_advect<D, S, T, MESH_UNIFORM, O>;
+    case MESH_DISPLACED: return k_advect<D, S, T, MESH_DISPLACED, O>;
     default:
-        if constexpr (D == 3) return PIC_OCT_LDS ? k_advect_oct<S, T> : k_advect<D, S, T, MESH_OCTREE>;
+        if constexpr (D == 3) {
+            if constexpr (O) return k_advect<D, S, T, MESH_OCTREE, true>;
+            else return PIC_OCT_LDS ? k_advect_oct<S, T> : k_advect<D, S, T, MESH_OCTREE>;
+        }
         return nullptr;
     }
 }
-template <int D, int S> AdvectFn advect_for_prec(int prec, int kind)
+template <int D, int S, bool O> AdvectFn advect_for_prec(int prec, int kind)
 {
-    return prec == PIC_F32 ? advect_for_kind<D, S, float>(kind) : advect_for_kind<D, S, double>(kind);
+    return prec == PIC_F32 ? advect_for_kind<D, S, float, O>(kind) : advect_for_kind<D, S, double, O>(kind);
 }
-template <int D> AdvectFn advect_for_scheme(int scheme, int prec, int kind)
+template <int D, bool O> AdvectFn advect_for_scheme(int scheme, int prec, int kind)
 {
     switch (scheme) {
-    case PIC_EULER: return advect_for_prec<D, 1>(prec, kind);
-    case PIC_RK2: return advect_for_prec<D, 2>(prec, kind);
-    case PIC_RK4: return advect_for_prec<D, 4>(prec, kind);
+    case PIC_EULER: return advect_for_prec<D, 1, O>(prec, kind);
+    case PIC_RK2: return advect_for_prec<D, 2, O>(prec, kind);
+    case PIC_RK4: return advect_for_prec<D, 4, O>(prec, kind);
     }
     return nullptr;
 }
-AdvectFn advect_kernel(int dim, int scheme, int prec, int kind)
+AdvectFn advect_kernel(int dim, int scheme, int prec, int kind, bool ode = false)
 {
-    return dim == 2 ? advect_for_scheme<2>(scheme, prec, kind) : advect_for_scheme<3>(scheme, prec, kind);
+    if (ode) return dim == 2 ? advect_for_scheme<2, true>(scheme, prec, kind) : advect_for_scheme<3, true>(scheme, prec, kind);
+    return dim == 2 ? advect_for_scheme<2, false>(scheme, prec, kind) : advect_for_scheme<3, false>(scheme, prec, kind);
 }
 
 pic_status require_ready(pic_ctx *c, bool field)
@@ -436,22 +440,22 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
 }
 
 using BlockFn = void (*)(const ProblemDev *, const BlockItem *, int);
-template <int D, int S, bool F> BlockFn block_for_prec(int prec)
+template <int D, int S, bool F, bool O> BlockFn block_for_prec(int prec)
 {
     if constexpr (D == 3) {
-        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2], F>;
-        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2], F>;
+        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2], F, O>;
+        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2], F, O>;
     } else {
-        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1, F>;
-        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1, F>;
+        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1, F, O>;
+        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1, F, O>;
     }
 }
-template <int D, bool F = false> BlockFn block_for_scheme(int scheme, int prec)
+template <int D, bool F, bool O> BlockFn block_for_scheme(int scheme, int prec)
 {
     switch (scheme) {
-    case PIC_EULER: return block_for_prec<D, 1, F>(prec);
-    case PIC_RK2: return block_for_prec<D, 2, F>(prec);
-    case PIC_RK4: return block_for_prec<D, 4, F>(prec);
+    case PIC_EULER: return block_for_prec<D, 1, F, O>(prec);
+    case PIC_RK2: return block_for_prec<D, 2, F, O>(prec);
+    case PIC_RK4: return block_for_prec<D, 4, F, O>(prec);
     }
     return nullptr;
 }
@@ -477,10 +481,15 @@ BlockFn batch_block_kernel(int dim, int scheme, int variant)
     return S == 1 ? shape_kernel_v<3, 1>(variant) : S == 2 ? shape_kernel_v<3, 2>(variant) : shape_kernel_v<3, 4>(variant);
 }
 
-BlockFn block_kernel(int dim, int scheme, int prec, bool fused)
+// ode: with the property equations (the problem's odes flag)
+BlockFn block_kernel(int dim, int scheme, int prec, bool fused, bool ode = false)
 {
-    if (dim == 2) return fused ? block_for_scheme<2, true>(scheme, prec) : block_for_scheme<2, false>(scheme, prec);
-    return fused ? block_for_scheme<3, true>(scheme, prec) : block_for_scheme<3, false>(scheme, prec);
+    if (ode) {
+        if (dim == 2) return fused ? block_for_scheme<2, true, true>(scheme, prec) : block_for_scheme<2, false, true>(scheme, prec);
+        return fused ? block_for_scheme<3, true, true>(scheme, prec) : block_for_scheme<3, false, true>(scheme, prec);
+    }
+    if (dim == 2) return fused ? block_for_scheme<2, true, false>(scheme, prec) : block_for_scheme<2, false, false>(scheme, prec);
+    return fused ? block_for_scheme<3, true, false>(scheme, prec) : block_for_scheme<3, false, false>(scheme, prec);
 }
 
 #ifndef PIC_FUSE_STEPS
@@ -492,8 +501,9 @@ BlockFn block_kernel(int dim, int scheme, int prec, bool fused)
 pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec, int n)
 {
     const int pr = prec == PIC_F32;
-    BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false);
-    BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true);
+    const bool ode = dp == c->d_prob && c->h_prob.odes != 0;
+    BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false, ode);
+    BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true, ode);
     LAUNCH(c, "advect", fa, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0);
@@ -508,14 +518,15 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
 
 pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
 {
+    const bool ode = dp == c->d_prob && c->h_prob.odes != 0;
     if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
-        BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false);
+        BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false, ode);
         const int pr = prec == PIC_F32;
         LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
                c->n_blk[pr]);
         return enqueue_sort(c, dp, 1);
     }
-    AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind);
+    AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind, ode);
     if (!f) return fail(c, PIC_EINVAL, "unsupported combination dim=%d scheme=%d kind=%d", c->mesh.dim, scheme, c->mesh.kind);
     LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
     return enqueue_sort(c, dp, 1);
@@ -912,6 +923,30 @@ extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint
 // ===========================================================================
 // advance
 // ===========================================================================
+extern "C" pic_status pic_set_property_odes(pic_ctx *c, int32_t damage_prop, int32_t deform_prop, double alpha,
+                                            double beta)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (damage_prop < 0 && deform_prop < 0) {
+        c->h_prob.odes = 0;
+        return upload_problem(c);
+    }
+    const int d = c->mesh.dim, np = c->store.n_prop;
+    if (c->store.prop_prec != PIC_F64) return fail(c, PIC_EINVAL, "property equations need double-precision properties");
+    if (damage_prop < 0 || deform_prop < 0 || damage_prop >= np || deform_prop + d * d > np)
+        return fail(c, PIC_EINVAL, "damage_prop and deform_prop .. deform_prop + dim^2 - 1 must be properties");
+    if (damage_prop >= deform_prop && damage_prop < deform_prop + d * d)
+        return fail(c, PIC_EINVAL, "the damage property lies inside the deformation gradient");
+    if (!(std::isfinite(alpha) && std::isfinite(beta))) return fail(c, PIC_EINVAL, "alpha and beta must be finite");
+    c->h_prob.odes = 1;
+    c->h_prob.ode_dmg = damage_prop;
+    c->h_prob.ode_F = deform_prop;
+    c->h_prob.ode_alpha = alpha;
+    c->h_prob.ode_beta = beta;
+    return upload_problem(c);
+}
+
 extern "C" pic_status pic_advance(pic_ctx *c, double dt, int32_t n_steps, int32_t scheme, int32_t eval_prec)
 {
     pic_status s = require_ready(c, true);

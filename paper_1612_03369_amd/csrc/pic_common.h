@@ -853,6 +853,106 @@ __device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_
     }
 }
 
+// physical gradient G[c][j] = d u_c / d x_j at (K, t)
+template <int D, int KIND>
+__device__ __forceinline__ void grad_phys(const MeshDev &m, const typename NodeVec<D, double>::type *U, int64_t K,
+                                          const double *t, double G[3][3])
+{
+    double Gr[3][3];
+    eval_q2_refgrad<D, KIND>(m, U, K, t, Gr);
+    if constexpr (KIND == MESH_DISPLACED) {
+        double J[3][3];
+        map_jacobian<D, KIND>(m, K, t, J);
+        // G = Gr J^{-1}: row c solves J^T g = Gr[c]
+        double JT[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) JT[a][b] = J[b][a];
+        for (int c = 0; c < D; ++c) {
+            double s[3];
+            solve_small<D>(JT, Gr[c], s);
+            for (int j = 0; j < D; ++j) G[c][j] = s[j];
+        }
+    } else {
+        double x0[3], h[3];
+        cell_box<KIND>(m, K, x0, h);
+        for (int c = 0; c < D; ++c)
+            for (int j = 0; j < D; ++j) G[c][j] = Gr[c][j] / h[j];
+    }
+}
+
+// Reference gradient Gr[c][r] = d u_c / d xhat_r of the Q2 field on a node
+// grid (base / sy / sz as in eval_q2_at), accumulated in T.
+template <int D, typename T, typename Ptr, typename I>
+__device__ __forceinline__ void grad_q2_at(Ptr U, I base, I sy, I sz, const double *tr, double Gr[3][3])
+{
+    T l[3][3], dl[3][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        lag3((T)tr[a], l[a]);
+        dlag3((T)tr[a], dl[a]);
+    }
+    T g[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[c][r] = T(0);
+#pragma unroll 1
+    for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const auto v = U[base + a + sy * b + sz * c3];
+                T w[3];
+                if constexpr (D == 2) {
+                    w[0] = dl[0][a] * l[1][b];
+                    w[1] = l[0][a] * dl[1][b];
+                    w[2] = T(0);
+                } else {
+                    w[0] = dl[0][a] * l[1][b] * l[2][c3];
+                    w[1] = l[0][a] * dl[1][b] * l[2][c3];
+                    w[2] = l[0][a] * l[1][b] * dl[2][c3];
+                }
+                const T vc[3] = {(T)nv_x(v), (T)nv_y(v), D == 3 ? (T)nv_z(v) : T(0)};
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+#pragma unroll
+                    for (int r = 0; r < D; ++r) g[c][r] = fma_t(vc[c], w[r], g[c][r]);
+            }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Gr[c][r] = (double)g[c][r];
+}
+
+// Property equations integrated along the trajectory (Sec. 2.6), at a point
+// with velocity gradient G[i][j] = d u_i / d x_j:
+//   damage d' = alpha |eps| - beta d, eps = (G + G^T)/2, |.| Frobenius norm;
+//   deformation gradient F' = G F (F row-major, D x D).
+template <int D>
+__device__ __forceinline__ void prop_rates(const double G[3][3], double alpha, double beta, double dmg, const double *F,
+                                           double &ddmg, double *dF)
+{
+    double e2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double e = 0.5 * (G[i][j] + G[j][i]);
+            e2 = fma(e, e, e2);
+        }
+    ddmg = alpha * sqrt(e2) - beta * dmg;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc = fma(G[i][k], F[k * D + j], acc);
+            dF[i * D + j] = acc;
+        }
+}
+
 // ---------------------------------------------------------------------------
 // XCD-aware work mapping.  Workgroups are dealt to the eight XCDs round robin
 // (workgroup b runs on XCD b mod 8) and each XCD has its own L2.  Workgroup b

@@ -13,6 +13,10 @@ struct ProblemDev {
     int cur;                 // index of the current buffer
     int n_prop, prop_f64;
     int pop_min, pop_max;
+    // property equations integrated with the positions (off unless odes != 0):
+    // damage in prop[ode_dmg], deformation gradient in prop[ode_F .. ode_F + dim^2)
+    int odes, ode_dmg, ode_F;
+    double ode_alpha, ode_beta;
     int64_t cap;
     double dt;
     const void *u64;         // repacked field, double

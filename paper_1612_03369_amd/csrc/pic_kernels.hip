@@ -79,6 +79,78 @@ __device__ __forceinline__ uint32_t advect_one(const MeshDev &m, const typename 
     return advect_one_e<D, S, KIND>(m, ev, dt, x, t, K, near, ls);
 }
 
+// The same step for the position and the property equations as one system
+// (damage and deformation gradient, Pp = [d, F_00, F_01, ...]): every stage
+// evaluates u and grad u at its point; gr(K, t, G) gives the physical
+// gradient in cell K.  Positions take exactly the operations of advect_one_e.
+template <int D, int S, int KIND, class Eval, class Grad>
+__device__ __forceinline__ uint32_t advect_one_e_ode(const MeshDev &m, Eval &&ev, Grad &&gr, double dt, double alpha,
+                                                     double beta, double *x, double *t, double *Pp, int32_t K,
+                                                     bool &near, LocStats &ls)
+{
+    constexpr int NP = 1 + D * D;
+    constexpr int NS = S == 1 ? 1 : (S == 2 ? 2 : 4);
+    double u[3], G[3][3], kx[4][3], kP[4][NP], y[3], ty[3], Ps[NP];
+    int32_t Ky = K;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (s == 0) {
+            ev(K, t, u);
+            gr(K, t, G);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Ps[q] = Pp[q];
+        } else {
+            const double c = (S == 4 && s == 3) ? 1.0 : 0.5;
+#pragma unroll
+            for (int a = 0; a < D; ++a) y[a] = x[a] + c * kx[s - 1][a];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Ps[q] = Pp[q] + c * kP[s - 1][q];
+            near |= near_boundary<D>(m, y);
+            if (!locate<D, KIND>(m, y, s == 1 ? K : Ky, Ky, ty, ls)) return LOST;
+            ev(Ky, ty, u);
+            gr(Ky, ty, G);
+        }
+        double dd, dF[D * D];
+        prop_rates<D>(G, alpha, beta, Ps[0], Ps + 1, dd, dF);
+#pragma unroll
+        for (int a = 0; a < D; ++a) kx[s][a] = dt * u[a];
+        kP[s][0] = dt * dd;
+#pragma unroll
+        for (int q = 0; q < D * D; ++q) kP[s][1 + q] = dt * dF[q];
+    }
+    double xn[3], Pn[NP];
+    if constexpr (S == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + kx[0][a];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Pn[q] = Pp[q] + kP[0][q];
+    } else if constexpr (S == 2) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + kx[1][a];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Pn[q] = Pp[q] + kP[1][q];
+    } else {
+        const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + kx[0][a] * s6 + kx[1][a] * s3 + kx[2][a] * s3 + kx[3][a] * s6;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Pn[q] = Pp[q] + kP[0][q] * s6 + kP[1][q] * s3 + kP[2][q] * s3 + kP[3][q] * s6;
+    }
+    near |= near_boundary<D>(m, xn);
+    int32_t Kn;
+    double tn[3];
+    if (!locate<D, KIND>(m, xn, K, Kn, tn, ls)) return LOST;
+    near |= face_dist<D>(tn) < NEAR_TOL;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = xn[a];
+        t[a] = tn[a];
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) Pp[q] = Pn[q];
+    return (uint32_t)Kn;
+}
+
 // Uniform meshes: the same step with (i,j,k) carried along (no index division
 // after the first) and the closed-form location.
 template <int D, int S, typename T>
@@ -167,7 +239,7 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, int slot,
 #else
 #define PIC_ADVECT_ATTR
 #endif
-template <int D, int S, typename T, int KIND>
+template <int D, int S, typename T, int KIND, bool ODE = false>
 __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemDev *__restrict__ probs,
                                                                   const WorkItem *__restrict__ work, int n_work)
 {
@@ -197,7 +269,24 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
             }
             bool near = false;
             uint32_t key;
-            if constexpr (KIND == MESH_UNIFORM) {
+            double Pp[1 + D * D];
+            if constexpr (ODE) {
+                auto pin = (gptr<double>)cur.prop;
+                Pp[0] = pin[P.ode_dmg * cap + i];
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) Pp[1 + q] = pin[(P.ode_F + q) * cap + i];
+                const auto *U = reinterpret_cast<const typename NodeVec<D, T>::type *>(sizeof(T) == 4 ? P.u32 : P.u64);
+                const auto *U64 = reinterpret_cast<const typename NodeVec<D, double>::type *>(P.u64);
+                auto ev = [&](int32_t Kc, const double *tc, double *uc) { eval_q2<D, T, KIND>(m, U, Kc, tc, uc); };
+                auto gr = [&](int32_t Kc, const double *tc, double G[3][3]) { grad_phys<D, KIND>(m, U64, Kc, tc, G); };
+                key = advect_one_e_ode<D, S, KIND>(m, ev, gr, dt, P.ode_alpha, P.ode_beta, x, t, Pp, K, near, ls);
+                if (key != LOST) {
+                    auto po = (gptr_mut<double>)cur.prop;
+                    po[P.ode_dmg * cap + i] = Pp[0];
+#pragma unroll
+                    for (int q = 0; q < D * D; ++q) po[(P.ode_F + q) * cap + i] = Pp[1 + q];
+                }
+            } else if constexpr (KIND == MESH_UNIFORM) {
                 using V = typename NodeVec<D, T>::type;
                 auto U = (gptr<V>)(sizeof(T) == 4 ? P.u32 : P.u64);
                 key = advect_one_uniform<D, S, T>(m, U, dt, x, t, (uint32_t)K, near);
@@ -436,6 +525,109 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, gptr<typena
  * buffer.  A fused step is thus "finish the previous step's permutation and
  * compute the next step's keys" in one pass over the particle state.
  */
+// Physical gradient of the field at the reference point t of cell ijk, from
+// the LDS window or the global node array (as eval_blk).
+template <int D, typename T, int BX, int BY, int BZ>
+__device__ __forceinline__ void grad_blk(const MeshDev &m, gptr<typename NodeVec<D, T>::type> Ug,
+                                         const typename NodeVec<D, T>::type *W, const int *b0, const int ijk[3],
+                                         const double *t, double G[3][3])
+{
+    using Sh = BlockShape<D, BX, BY, BZ>;
+    const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;
+    bool in = ((unsigned)di < (unsigned)Sh::CX) & ((unsigned)dj < (unsigned)Sh::CY);
+    if constexpr (D == 3) in &= (unsigned)dk < (unsigned)Sh::CZ;
+    double Gr[3][3];
+    if (in) {
+        const int base = 2 * di + Sh::WX * (2 * dj + (D == 3 ? Sh::WY * 2 * dk : 0));
+        grad_q2_at<D, T>(W, base, (int)Sh::WX, (int)(Sh::WX * Sh::WY), t, Gr);
+    } else {
+        const int64_t sz = (int64_t)m.nnx * m.nny;
+        const int64_t base = 2 * ijk[0] + (int64_t)m.nnx * (2 * ijk[1]) + (D == 3 ? sz * (2 * ijk[2]) : 0);
+        grad_q2_at<D, T>(Ug, base, (int64_t)m.nnx, sz, t, Gr);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int j = 0; j < D; ++j) G[c][j] = Gr[c][j] * m.inv_h[j];
+}
+
+// advect_one_blk with the property equations (Pp = [d, F_00, F_01, ...]):
+// positions take exactly the operations of advect_one_blk; every stage also
+// evaluates grad u at its point and the property rates at its property values.
+template <int D, int S, typename T, int BX, int BY, int BZ>
+__device__ __forceinline__ uint32_t advect_one_blk_ode(const MeshDev &m, gptr<typename NodeVec<D, T>::type> Ug,
+                                                       const typename NodeVec<D, T>::type *W, const int *b0, double dt,
+                                                       double alpha, double beta, double *x, double *t, double *Pp,
+                                                       uint32_t K, bool &near)
+{
+    constexpr int NP = 1 + D * D;
+    constexpr int NS = S == 1 ? 1 : (S == 2 ? 2 : 4);
+    const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
+    int jk[3];
+    double u[3], G[3][3], y[3], ty[3], xn[3], k[3], Ps[NP], kP[4][NP];
+    ijk_of<D>(m, K, jk);
+    bool in = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (s == 0) {
+            eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, t, u);
+            grad_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, t, G);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Ps[q] = Pp[q];
+        } else {
+            const double c = (S == 4 && s == 3) ? 1.0 : 0.5;
+            in &= locate_stage<D>(m, y, jk, ty, near);
+            eval_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, u);
+            grad_blk<D, T, BX, BY, BZ>(m, Ug, W, b0, jk, ty, G);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Ps[q] = Pp[q] + c * kP[s - 1][q];
+        }
+        double dd, dF[D * D];
+        prop_rates<D>(G, alpha, beta, Ps[0], Ps + 1, dd, dF);
+        kP[s][0] = dt * dd;
+#pragma unroll
+        for (int q = 0; q < D * D; ++q) kP[s][1 + q] = dt * dF[q];
+        // positions: the operations of advect_one_blk
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if constexpr (S == 1) {
+                xn[a] = x[a] + dt * u[a];
+            } else if constexpr (S == 2) {
+                if (s == 0) y[a] = x[a] + 0.5 * (dt * u[a]);
+                else xn[a] = x[a] + dt * u[a];
+            } else {
+                if (s < 3) {
+                    k[a] = dt * u[a];
+                    xn[a] = s == 0 ? x[a] + k[a] * s6 : xn[a] + k[a] * s3;
+                    y[a] = s < 2 ? x[a] + 0.5 * k[a] : x[a] + k[a];
+                } else {
+                    xn[a] = xn[a] + (dt * u[a]) * s6;
+                }
+            }
+        }
+    }
+    double Pn[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        if constexpr (S == 1) Pn[q] = Pp[q] + kP[0][q];
+        else if constexpr (S == 2) Pn[q] = Pp[q] + kP[1][q];
+        else Pn[q] = Pp[q] + kP[0][q] * s6 + kP[1][q] * s3 + kP[2][q] * s3 + kP[3][q] * s6;
+    }
+    near |= near_boundary<D>(m, xn);
+    double tn[3];
+    in &= locate_uniform<D>(m, xn, jk, tn);
+    if (!in) return LOST;
+    near |= face_dist<D>(tn) < NEAR_TOL;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = xn[a];
+        t[a] = tn[a];
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) Pp[q] = Pn[q];
+    return cell_of<D>(m, jk);
+}
+
 #ifndef PIC_ADV_THREADS
 #define PIC_ADV_THREADS 256         // threads per workgroup of the block kernels
 #endif
@@ -452,8 +644,8 @@ template <int D, typename T> struct BlkWaves {
 #define PIC_BLK_PREFETCH 2          // 1: load the next particle's state while advancing this one; 2: also its gather source one step earlier
 #endif
 constexpr int ADV_BLOCK = PIC_ADV_THREADS;
-template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED>
-__global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
+template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED, bool ODE = false>
+__global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ? 1 : BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
                                                                       const BlockItem *__restrict__ work, int n_work)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
@@ -588,7 +780,18 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
                 fetch(f + ADV_BLOCK);
             }
             bool near = false;
-            const uint32_t key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Ug, s_w, b0, dt, x, t, (uint32_t)K, near);
+            uint32_t key;
+            double Pp[1 + D * D];
+            if constexpr (ODE) {
+                auto pin = (gptr<double>)cur.prop;
+                Pp[0] = pin[P.ode_dmg * cap + sidx];
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) Pp[1 + q] = pin[(P.ode_F + q) * cap + sidx];
+                key = advect_one_blk_ode<D, S, T, BX, BY, BZ>(m, Ug, s_w, b0, dt, P.ode_alpha, P.ode_beta, x, t, Pp,
+                                                              (uint32_t)K, near);
+            } else {
+                key = advect_one_blk<D, S, T, BX, BY, BZ>(m, Ug, s_w, b0, dt, x, t, (uint32_t)K, near);
+            }
             if (key != LOST || FUSED) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
@@ -605,6 +808,15 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(BlkWa
                 } else {
                     for (int j = 0; j < P.n_prop; ++j)
                         ((float *)out.prop)[j * cap + p] = ((const float *)cur.prop)[j * cap + sidx];
+                }
+            }
+            if constexpr (ODE) {
+                // the integrated properties (double precision; in place when not fused)
+                if (key != LOST || FUSED) {
+                    auto po = (gptr_mut<double>)out.prop;
+                    po[P.ode_dmg * cap + p] = Pp[0];
+#pragma unroll
+                    for (int q = 0; q < D * D; ++q) po[(P.ode_F + q) * cap + p] = Pp[1 + q];
                 }
             }
             key_out[p] = key;

@@ -27,14 +27,18 @@ def oracle_store(cfg, n_prop=None, mesh=None, cap=None):
     return om, st
 
 
-def oracle_run_tracking(om, U, dt, scheme, steps, st):
-    """Run the oracle step by step; return ids that were near a face at any step."""
+def oracle_run_tracking(om, U, dt, scheme, steps, st, odes=None):
+    """Run the oracle step by step; return ids that were near a face at any step.
+    odes = (alpha, beta, damage_prop, deform_prop) integrates the property equations too."""
     near_ids = set()
     lost = 0
     for _ in range(steps):
         n = st.n
         ids_before = st.id[:n].copy()
-        key, near = O.advect(om, U, dt, scheme, st)
+        if odes is None:
+            key, near = O.advect(om, U, dt, scheme, st)
+        else:
+            key, near = O.advect_odes(om, U, dt, scheme, st, *odes)
         near_ids |= set(ids_before[near.astype(bool)].tolist())
         lost += int((key == O.LOST).sum())
         perm, cs = O.stable_sort_perm(om.n_cells, st.cell[:n], key)

@@ -1,0 +1,193 @@
+"""GPU parity of the property equations of Sec. 2.6 (damage and deformation
+gradient integrated with the positions by the same RK scheme) against the
+FP64 oracle, on uniform, displaced and octree meshes; fused vs single steps."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1612_03369_amd import inputs as I
+
+from helpers import compare_stores, oracle_run_tracking
+
+pytestmark = pytest.mark.gpu
+
+ALPHA, BETA = 0.8, 1.7
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1612_03369_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _initial_props(dim, n, seed):
+    """[1 + dim^2][n]: damage, then F row-major (identity plus a perturbation)."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros((1 + dim * dim, n))
+    P[0] = rng.uniform(0.0, 0.5, n)
+    F = np.eye(dim)[None] + 0.2 * rng.standard_normal((n, dim, dim))
+    P[1:] = F.reshape(n, dim * dim).T
+    return P
+
+
+def _compare_props(g, o, near, tol):
+    common = np.intersect1d(g["id"], o["id"])
+    common = common[~np.isin(common, np.array(sorted(near), dtype=np.uint32))]
+    gi = np.argsort(g["id"])
+    oi = np.argsort(o["id"])
+    gp = gi[np.searchsorted(g["id"][gi], common)]
+    op = oi[np.searchsorted(o["id"][oi], common)]
+    a, b = g["prop"][:, gp], o["prop"][:, op]
+    err = (np.abs(a - b) / np.maximum(1.0, np.abs(b))).max()
+    assert err <= tol, err
+    return err, common.size
+
+
+def _gpu_run(p, cfg, dim, dt, scheme, steps, prec, fused=True):
+    P0 = _initial_props(dim, cfg["xr"].shape[1], 77)
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"], prop=P0)
+    p.set_property_odes(0, 1, ALPHA, BETA)
+    if fused:
+        p.advance(dt, steps, scheme, prec)
+    else:
+        for _ in range(steps):
+            p.advance(dt, 1, scheme, prec)
+    return p.numpy()
+
+
+def _oracle_run(cfg, dim, om, U, dt, scheme, steps):
+    st = O.seed(om, cfg["counts"], cfg["xr"], cfg["ids"], 1 + dim * dim)
+    st.prop[:, : st.n] = _initial_props(dim, cfg["xr"].shape[1], 77)
+    near, _ = oracle_run_tracking(om, U, dt, scheme, steps, st, odes=(ALPHA, BETA, 0, 1))
+    return st, near
+
+
+def _run(L, p, cfg, om, U, dt, scheme, steps, prec):
+    dim = om.dim
+    g = _gpu_run(p, cfg, dim, dt, scheme, steps, prec)
+    st, near = _oracle_run(cfg, dim, om, U, dt, scheme, steps)
+    return g, st, near
+
+
+@pytest.mark.parametrize("dim,scheme,prec", [(3, 4, 0), (3, 2, 0), (3, 1, 0), (2, 4, 0), (2, 2, 0), (3, 4, 1)])
+def test_property_odes_uniform(L, dim, scheme, prec):
+    from paper_1612_03369_amd.api import Problem
+    _say(f"case: property equations, uniform dim={dim} scheme={scheme} prec={prec}")
+    n = 9 if dim == 3 else 19
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(dim, seed=1300 + dim).velocity, I.uniform_q2_nodes(mesh)))
+    counts = np.random.default_rng(1310).integers(0, 9, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=1320 + dim)
+    cfg = dict(mesh=mesh, counts=counts, xr=xr, ids=ids)
+    p = Problem(0)
+    p.mesh_uniform(dim, mesh.n[:dim])
+    p.set_velocity(U)
+    p.allocate(xr.shape[1], n_prop=1 + dim * dim, prop_dtype="float64")
+    om = O.OracleMesh.uniform(mesh)
+    dt, steps = 0.6 / n, 6
+    g, st, near = _run(L, p, cfg, om, U, dt, scheme, steps, prec)
+    if prec == 0:
+        err, nn = compare_stores(g, st.view(), near)
+        # F grows like exp(|grad u| t); rounding of the 27-term gradient sums (a different
+        # summation order on each side) grows with it: a few 1e-13 measured, 4e-12 allowed
+        perr, m = _compare_props(g, st.view(), near, 4e-12)
+    else:
+        # FP32 evaluation of u and grad u (positions accumulate in FP64): the positions keep the
+        # bound of the FP32 position test, the properties a relative 1e-4 away from cell changes
+        o = st.view()
+        common, gi, oi = np.intersect1d(g["id"], o["id"], return_indices=True)
+        err = np.abs(g["x"][:, gi] - o["x"][:, oi]).max()
+        assert err <= 1e-5, err
+        perr, m = _compare_props(g, o, near | _near_f32(g, o), 1e-4)
+    _say(f"  max position err {err:.2e}, max property err {perr:.2e} on {m} particles")
+    # fused steps = single steps, bit for bit, properties included
+    g2 = _gpu_run(p, cfg, dim, dt, scheme, steps, prec, fused=False)
+    for k in ("x", "xr", "cell", "id", "prop"):
+        assert np.array_equal(g[k], g2[k]), k
+    p.close()
+
+
+def _near_f32(g, o):
+    """ids whose FP32-evaluated cell differs from the oracle's (positions within rounding of a face)."""
+    gi = {int(i): k for k, i in enumerate(g["id"])}
+    bad = set()
+    for k, i in enumerate(o["id"]):
+        j = gi.get(int(i))
+        if j is None or g["cell"][j] != o["cell"][k]:
+            bad.add(int(i))
+    return bad | (set(g["id"].tolist()) ^ set(o["id"].tolist()))
+
+
+def test_property_odes_displaced_and_octree(L):
+    from paper_1612_03369_amd.api import Problem
+    _say("case: property equations on a displaced 3D mesh and on an octree")
+    # displaced
+    mesh = I.UniformMesh(3, (6, 5, 4))
+    vert = I.displaced_vertices(mesh, 0.15, seed=1401)
+    om = O.OracleMesh.displaced(mesh, vert)
+    nodes = om.q2_node_coords()
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=1402).velocity, nodes))
+    counts = np.random.default_rng(1403).integers(0, 7, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=1404)
+    cfg = dict(mesh=mesh, counts=counts, xr=xr, ids=ids)
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.mesh_displace(vert)
+    p.set_velocity(U)
+    p.allocate(xr.shape[1], n_prop=10, prop_dtype="float64")
+    g, st, near = _run(L, p, cfg, om, U, 0.08, 4, 5, 0)
+    err, nn = compare_stores(g, st.view(), near, check_order=False)
+    perr, m = _compare_props(g, st.view(), near, 1e-11)
+    _say(f"  displaced: max position err {err:.2e}, property err {perr:.2e} on {m}")
+    p.close()
+    # octree
+    level, anchor = I.octree_shell_leaves(base_level=1, max_level=4, r_in=0.0, r_out=0.3, width=1.0,
+                                          centre=(0.3, 0.35, 0.4))
+    level, anchor = I.balance_octree(level, anchor, 4)
+    om = O.OracleMesh.octree(level, anchor, 4)
+    nodes = om.q2_node_coords()
+    Uraw = I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=1405).velocity, nodes))
+    U = om.resolve_hanging(Uraw)
+    counts = np.random.default_rng(1406).integers(0, 6, level.size).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=1407)
+    cfg = dict(counts=counts, xr=xr, ids=ids)
+    p = Problem(0)
+    p.mesh_octree(level, anchor, 4)
+    p.set_velocity(Uraw)
+    p.allocate(xr.shape[1], n_prop=10, prop_dtype="float64")
+    g, st, near = _run(L, p, cfg, om, U, 0.5 / 16, 2, 6, 0)
+    err, nn = compare_stores(g, st.view(), near, check_order=False)
+    perr, m = _compare_props(g, st.view(), near, 1e-11)
+    _say(f"  octree: max position err {err:.2e}, property err {perr:.2e} on {m}")
+    p.close()
+
+
+def test_property_odes_argument_checks(L):
+    from paper_1612_03369_amd.api import Problem
+    from paper_1612_03369_amd._lib import PicError
+    mesh = I.UniformMesh(2, (4, 4))
+    p = Problem(0)
+    p.mesh_uniform(2, mesh.n[:2])
+    p.set_velocity(np.zeros((2, mesh.n_nodes)))
+    p.allocate(8, n_prop=5, prop_dtype="float32")
+    with pytest.raises(PicError):
+        p.set_property_odes(0, 1, 1.0, 1.0)            # float properties
+    p.allocate(8, n_prop=5, prop_dtype="float64")
+    with pytest.raises(PicError):
+        p.set_property_odes(0, 2, 1.0, 1.0)            # F would run past the last property
+    with pytest.raises(PicError):
+        p.set_property_odes(2, 1, 1.0, 1.0)            # damage inside F
+    p.set_property_odes(4, 0, 1.0, 1.0)
+    p.set_property_odes(-1, -1)
+    p.close()
