@@ -251,6 +251,8 @@ def run_main(args):
             extras["batch"] = bench_batch(args)
         if "octree" in args.extras:
             extras["octree"] = bench_octree(args)
+        if "odes" in args.extras:
+            extras["odes"] = bench_odes(args)
         line["extras"] = extras
 
     if not args.no_cpu_baseline:
@@ -427,6 +429,59 @@ def bench_octree(args):
     return r
 
 
+def bench_odes(args):
+    """The 64^3 RK4 workload with the damage and deformation-gradient equations (Sec. 2.6) integrated
+    with the positions: 1 + 9 double-precision properties per particle, same K fused steps."""
+    import numpy as np
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Problem
+
+    cfg = I.config2(eval_f32=True)
+    mesh = cfg["mesh"]
+    n0 = cfg["xr"].shape[1]
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n0, n_prop=10, prop_dtype="float64")
+    P0 = np.zeros((10, n0))
+    P0[[1, 5, 9]] = 1.0                              # d = 0, F = I
+    P0 = torch.as_tensor(P0).to(p.device)
+    dt = cfg["dt"]
+
+    def run():
+        p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"], prop=P0)
+        p.set_property_odes(0, 1, 1.0, 0.5)
+        p.stats_reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        p.advance(dt, args.steps, L.PIC_RK4, L.PIC_F32)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    run()
+    el = run()
+    st = p.stats()
+    p.profile(True)
+    run()
+    ms, n = p.profile_read("gather_advect")
+    p.profile(False)
+    g = p.current()
+    F = g["prop"][1:10]
+    detF = torch.linalg.det(F.T.reshape(-1, 3, 3)).double()
+    r = {"workload": cfg["name"] + "+damage+F", "particles": n0, "n_prop": 10, "steps": args.steps,
+         "ms_per_step": 1e3 * el / args.steps, "particle_steps_per_s": st["particle_steps"] / el,
+         "gather_advect_avg_us": 1e3 * ms / max(n, 1),
+         "detF_min_max": [float(detF.min()), float(detF.max())],
+         "damage_max": float(g["prop"][0].max())}
+    log(f"[bench] odes: {r['ms_per_step']:.3f} ms/step, {r['particle_steps_per_s']:.3e} p-s/s, "
+        f"gather_advect {r['gather_advect_avg_us']:.0f} us, det F in {r['detF_min_max']}")
+    p.close()
+    return r
+
+
 def cpu_baseline(args):
     """FP64 oracle on the host cores: the first steps of the same workload."""
     from oracle import oracle as O
@@ -457,7 +512,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--extras", default="adjoint,batch,octree", help="comma list: adjoint,batch,octree ('' for none)")
+    ap.add_argument("--extras", default="adjoint,batch,octree,odes", help="comma list: adjoint,batch,octree,odes ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
