@@ -75,6 +75,11 @@ def lib():
             L.orc_advect_odes.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
                                           C.c_int, C.c_int, P, P, P]
             L.orc_sort_perm.restype = C.c_int64
+            L.orc_advect_t.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P]
+            L.orc_advect_t.restype = None
+            L.orc_advect_odes_t.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int,
+                                            C.c_double, C.c_double, C.c_int, C.c_int, P, P, P]
+            L.orc_advect_odes_t.restype = None
             L.orc_sort_perm.argtypes = [C.c_int64, C.c_int64, P, P, P, P]
             L.orc_step.restype = C.c_int
             L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, P, P, P]
@@ -338,24 +343,41 @@ def step(mesh: OracleMesh, U, dt, scheme, st: OracleStore, stats: Stats | None =
     return s
 
 
-def advect(mesh: OracleMesh, U, dt, scheme, st: OracleStore):
-    """Advection + location without reordering; returns (key, near)."""
+def advect(mesh: OracleMesh, U, dt, scheme, st: OracleStore, U1=None, dt_u=None, since=0.0):
+    """Advection + location without reordering; returns (key, near).
+
+    With U1 the field changes in time (Sec. 2.3): U at t^n, U1 at t^n + dt_u, interpolated linearly in
+    time; the step covers [t^n + since, t^n + since + dt]."""
     U = np.ascontiguousarray(U, np.float64)
     key = np.zeros(max(st.n, 1), np.uint32)
     near = np.zeros(max(st.n, 1), np.uint8)
-    lib().orc_advect(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), C.byref(st.c),
-                     _p(key), _p(near))
+    if U1 is None:
+        lib().orc_advect(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), C.byref(st.c),
+                         _p(key), _p(near))
+    else:
+        U1 = np.ascontiguousarray(U1, np.float64)
+        assert U1.shape == U.shape and dt_u is not None and dt_u > 0
+        lib().orc_advect_t(C.byref(mesh.c), _p(U), _p(U1), U.shape[1], float(dt_u), float(since), float(dt),
+                           int(scheme), C.byref(st.c), _p(key), _p(near))
     return key[: st.n], near[: st.n]
 
 
-def advect_odes(mesh: OracleMesh, U, dt, scheme, st: OracleStore, alpha, beta, damage_prop, deform_prop):
+def advect_odes(mesh: OracleMesh, U, dt, scheme, st: OracleStore, alpha, beta, damage_prop, deform_prop,
+                U1=None, dt_u=None, since=0.0):
     """Advection + location with the damage and deformation-gradient equations of Sec. 2.6 integrated
-    by the same RK scheme (no reordering); returns (key, near)."""
+    by the same RK scheme (no reordering); returns (key, near).  U1, dt_u, since as in advect."""
     U = np.ascontiguousarray(U, np.float64)
     key = np.zeros(max(st.n, 1), np.uint32)
     near = np.zeros(max(st.n, 1), np.uint8)
-    lib().orc_advect_odes(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), float(alpha), float(beta),
-                          int(damage_prop), int(deform_prop), C.byref(st.c), _p(key), _p(near))
+    if U1 is None:
+        lib().orc_advect_odes(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), float(alpha),
+                              float(beta), int(damage_prop), int(deform_prop), C.byref(st.c), _p(key), _p(near))
+    else:
+        U1 = np.ascontiguousarray(U1, np.float64)
+        assert U1.shape == U.shape and dt_u is not None and dt_u > 0
+        lib().orc_advect_odes_t(C.byref(mesh.c), _p(U), _p(U1), U.shape[1], float(dt_u), float(since), float(dt),
+                                int(scheme), float(alpha), float(beta), int(damage_prop), int(deform_prop),
+                                C.byref(st.c), _p(key), _p(near))
     return key[: st.n], near[: st.n]
 
 

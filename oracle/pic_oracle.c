@@ -15,6 +15,8 @@
  *   - stored reference location kept in sync with the location         Sec. 2.1, remark on reference coordinates
  *   - reference-local generation: x = Phi_K(xhat), only Phi_K needed   Sec. 2.2, remark on local generation
  *   - forward Euler / RK2 / RK4                                        Sec. 2.3 (readings below)
+ *   - field interpolated linearly in time between u^n and u^{n+1},
+ *     particle steps that sub-divide the field step                   Sec. 2.3
  *   - field evaluation through the shape functions on the reference cell  Sec. 2.3
  *   - in-cell test after every (sub)step via xhat in Khat              Sec. 2.4
  *   - discard particles leaving the domain (option 3)                  Sec. 2.4
@@ -40,6 +42,10 @@
  *        in index order; new properties = mean of the cell's survivors, or the
  *        initial function (initial position) for an empty cell.
  *   Adjoint: reverse sweep of the RK stages for L = (1/Nv) sum |x(T) - x*|^2.
+ *   Time interpolation: the two fields are evaluated at the point and combined,
+ *        u~(x, t) = u^n(x) + theta (u^{n+1}(x) - u^n(x)), theta = (t - t^n) / dt_u;
+ *        stage times t + 0, dt/2 (RK2; RK4 stages 2 and 3), dt (RK4 stage 4),
+ *        with t the particle step's start; theta > 1 extrapolates.
  *
  * Meshes:
  *   kind 0: uniform box mesh, closed-form locate by floor.
@@ -450,6 +456,40 @@ static void eval_grad(const orc_mesh *m, const double *U, int64_t n_nodes, int64
     }
 }
 
+/*
+ * Velocity over one field step (Sec. 2.3): u^n = U0 and, when the field
+ * changes in time, u^{n+1} = U1 (NULL: steady field).  `since` is the time
+ * elapsed since t^n; the two fields are evaluated at the point and combined
+ * linearly in time.
+ */
+typedef struct {
+    const double *U0, *U1;
+    int64_t nn;
+    double dt_u;
+} orc_field;
+
+static void field_eval(const orc_mesh *m, const orc_field *f, double since, int64_t K, const double *xr, double *u)
+{
+    orc_eval(m, f->U0, f->nn, K, xr, u);
+    if (!f->U1) return;
+    double u1[3];
+    orc_eval(m, f->U1, f->nn, K, xr, u1);
+    double theta = since / f->dt_u;
+    for (int a = 0; a < m->dim; ++a) u[a] = u[a] + theta * (u1[a] - u[a]);
+}
+
+static void field_grad(const orc_mesh *m, const orc_field *f, double since, int64_t K, const double *xr,
+                       double G[3][3])
+{
+    eval_grad(m, f->U0, f->nn, K, xr, G);
+    if (!f->U1) return;
+    double G1[3][3];
+    eval_grad(m, f->U1, f->nn, K, xr, G1);
+    double theta = since / f->dt_u;
+    for (int c = 0; c < m->dim; ++c)
+        for (int j = 0; j < m->dim; ++j) G[c][j] = G[c][j] + theta * (G1[c][j] - G[c][j]);
+}
+
 /* ------------------------------------------------------------------ */
 /* store                                                               */
 /* ------------------------------------------------------------------ */
@@ -493,52 +533,53 @@ int orc_seed(const orc_mesh *m, const int32_t *counts, const double *xr_in, int6
     return 0;
 }
 
-/* u at an arbitrary point: locate, then evaluate.  Returns 0 if outside. */
-static int velocity_at(const orc_mesh *m, const double *U, int64_t nn, const double *y, double *u,
+/* u at an arbitrary point and time: locate, then evaluate.  Returns 0 if outside. */
+static int velocity_at(const orc_mesh *m, const orc_field *f, double since, const double *y, double *u,
                        int32_t *cell_out, double *xr_out)
 {
     int32_t K;
     double t[3];
     if (!orc_locate(m, y, &K, t)) return 0;
-    orc_eval(m, U, nn, K, t, u);
+    field_eval(m, f, since, K, t, u);
     if (cell_out) *cell_out = K;
     if (xr_out) memcpy(xr_out, t, sizeof(double) * m->dim);
     return 1;
 }
 
 /*
- * Advance one particle by one step.  Stage 1 uses the stored (K, xhat) without
- * a locate.  Returns 1 if the particle survives; sets *near if any stage point
- * or the end point is within the near-face band.
+ * Advance one particle by one step of length dt that starts `since` after
+ * t^n.  Stage 1 uses the stored (K, xhat) without a locate.  Returns 1 if the
+ * particle survives; sets *near if any stage point or the end point is within
+ * the near-face band.
  */
-static int advect_one(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme,
+static int advect_one(const orc_mesh *m, const orc_field *f, double since, double dt, int scheme,
                       const double *x, int32_t K, const double *xr,
                       double *xn, int32_t *Kn, double *xrn, int *near)
 {
     int d = m->dim;
     double k1[3], k2[3], k3[3], k4[3], y[3], u[3];
     *near = 0;
-    orc_eval(m, U, nn, K, xr, u);
+    field_eval(m, f, since, K, xr, u);
     for (int a = 0; a < d; ++a) k1[a] = dt * u[a];
     if (scheme == 1) {
         for (int a = 0; a < d; ++a) xn[a] = x[a] + k1[a];
     } else if (scheme == 2) {
         for (int a = 0; a < d; ++a) y[a] = x[a] + 0.5 * k1[a];
         if (near_boundary(m, y)) *near = 1;
-        if (!velocity_at(m, U, nn, y, u, NULL, NULL)) return 0;
+        if (!velocity_at(m, f, since + 0.5 * dt, y, u, NULL, NULL)) return 0;
         for (int a = 0; a < d; ++a) xn[a] = x[a] + dt * u[a];
     } else {
         for (int a = 0; a < d; ++a) y[a] = x[a] + 0.5 * k1[a];
         if (near_boundary(m, y)) *near = 1;
-        if (!velocity_at(m, U, nn, y, u, NULL, NULL)) return 0;
+        if (!velocity_at(m, f, since + 0.5 * dt, y, u, NULL, NULL)) return 0;
         for (int a = 0; a < d; ++a) k2[a] = dt * u[a];
         for (int a = 0; a < d; ++a) y[a] = x[a] + 0.5 * k2[a];
         if (near_boundary(m, y)) *near = 1;
-        if (!velocity_at(m, U, nn, y, u, NULL, NULL)) return 0;
+        if (!velocity_at(m, f, since + 0.5 * dt, y, u, NULL, NULL)) return 0;
         for (int a = 0; a < d; ++a) k3[a] = dt * u[a];
         for (int a = 0; a < d; ++a) y[a] = x[a] + k3[a];
         if (near_boundary(m, y)) *near = 1;
-        if (!velocity_at(m, U, nn, y, u, NULL, NULL)) return 0;
+        if (!velocity_at(m, f, since + dt, y, u, NULL, NULL)) return 0;
         for (int a = 0; a < d; ++a) k4[a] = dt * u[a];
         for (int a = 0; a < d; ++a)
             xn[a] = x[a] + k1[a] / 6.0 + k2[a] / 3.0 + k3[a] / 3.0 + k4[a] / 6.0;
@@ -554,8 +595,8 @@ static int advect_one(const orc_mesh *m, const double *U, int64_t nn, double dt,
  * Writes the new location and reference location in place and the new cell
  * (or ORC_LOST) into key[i]; near[i] = 1 for near-face particles.
  */
-void orc_advect(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme,
-                orc_store *s, uint32_t *key, uint8_t *near)
+static void advect_all(const orc_mesh *m, const orc_field *f, double since, double dt, int scheme,
+                       orc_store *s, uint32_t *key, uint8_t *near)
 {
     int d = m->dim;
     int64_t cap = s->cap;
@@ -568,7 +609,7 @@ void orc_advect(const orc_mesh *m, const double *U, int64_t nn, double dt, int s
             x[a] = s->x[a * cap + i];
             t[a] = s->xr[a * cap + i];
         }
-        int alive = advect_one(m, U, nn, dt, scheme, x, s->cell[i], t, xn, &Kn, tn, &nf);
+        int alive = advect_one(m, f, since, dt, scheme, x, s->cell[i], t, xn, &Kn, tn, &nf);
         near[i] = (uint8_t)nf;
         if (!alive) {
             key[i] = ORC_LOST;
@@ -580,6 +621,25 @@ void orc_advect(const orc_mesh *m, const double *U, int64_t nn, double dt, int s
         }
         key[i] = (uint32_t)Kn;
     }
+}
+
+void orc_advect(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme,
+                orc_store *s, uint32_t *key, uint8_t *near)
+{
+    orc_field f = {U, NULL, nn, 1.0};
+    advect_all(m, &f, 0.0, dt, scheme, s, key, near);
+}
+
+/*
+ * orc_advect in a field that changes in time (Sec. 2.3): u^n = U0 at t^n,
+ * u^{n+1} = U1 at t^n + dt_u, the particle step [t^n + since, t^n + since + dt]
+ * (a sub-step when dt < dt_u).
+ */
+void orc_advect_t(const orc_mesh *m, const double *U0, const double *U1, int64_t nn, double dt_u, double since,
+                  double dt, int scheme, orc_store *s, uint32_t *key, uint8_t *near)
+{
+    orc_field f = {U0, U1, nn, dt_u};
+    advect_all(m, &f, since, dt, scheme, s, key, near);
 }
 
 /* ------------------------------------------------------------------ */
@@ -617,7 +677,7 @@ static void prop_rhs(int dim, const double G[3][3], double alpha, double beta, d
  * the stage's property values.  Stage 1 uses the stored (K, xhat).
  * P = [d, F_00, F_01, ...] (1 + dim^2 values).
  */
-static int advect_one_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme, double alpha,
+static int advect_one_odes(const orc_mesh *m, const orc_field *f, double since, double dt, int scheme, double alpha,
                            double beta, const double *x, int32_t K, const double *xr, const double *P,
                            double *xn, int32_t *Kn, double *xrn, double *Pn, int *near)
 {
@@ -628,17 +688,17 @@ static int advect_one_odes(const orc_mesh *m, const double *U, int64_t nn, doubl
     *near = 0;
     for (int s = 0; s < ns; ++s) {
         if (s == 0) {
-            orc_eval(m, U, nn, K, xr, u);
-            eval_grad(m, U, nn, K, xr, G);
+            field_eval(m, f, since, K, xr, u);
+            field_grad(m, f, since, K, xr, G);
             for (int q = 0; q < np; ++q) Ps[q] = P[q];
         } else {
-            /* RK2: midpoint; RK4: x + k1/2, x + k2/2, x + k3 */
+            /* RK2: midpoint; RK4: x + k1/2, x + k2/2, x + k3; the stage's time is t + c dt */
             double c = (scheme == 4 && s == 3) ? 1.0 : 0.5;
             for (int a = 0; a < d; ++a) y[a] = x[a] + c * kx[s - 1][a];
             for (int q = 0; q < np; ++q) Ps[q] = P[q] + c * kP[s - 1][q];
             if (near_boundary(m, y)) *near = 1;
-            if (!velocity_at(m, U, nn, y, u, &Ky, yr)) return 0;
-            eval_grad(m, U, nn, Ky, yr, G);
+            if (!velocity_at(m, f, since + c * dt, y, u, &Ky, yr)) return 0;
+            field_grad(m, f, since + c * dt, Ky, yr, G);
         }
         double dd, dF[9];
         prop_rhs(d, G, alpha, beta, Ps[0], Ps + 1, &dd, dF);
@@ -667,8 +727,8 @@ static int advect_one_odes(const orc_mesh *m, const double *U, int64_t nn, doubl
  * the deformation gradient in properties deform_prop .. deform_prop + dim^2 - 1
  * (row-major).  Both must be given (>= 0).
  */
-void orc_advect_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme, double alpha, double beta,
-                     int damage_prop, int deform_prop, orc_store *s, uint32_t *key, uint8_t *near)
+static void advect_odes_all(const orc_mesh *m, const orc_field *f, double since, double dt, int scheme, double alpha,
+                            double beta, int damage_prop, int deform_prop, orc_store *s, uint32_t *key, uint8_t *near)
 {
     int d = m->dim, np = 1 + d * d;
     int64_t cap = s->cap;
@@ -683,7 +743,7 @@ void orc_advect_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, 
         }
         P[0] = s->prop[damage_prop * cap + i];
         for (int q = 0; q < d * d; ++q) P[1 + q] = s->prop[(deform_prop + q) * cap + i];
-        int alive = advect_one_odes(m, U, nn, dt, scheme, alpha, beta, x, s->cell[i], t, P, xn, &Kn, tn, Pn, &nf);
+        int alive = advect_one_odes(m, f, since, dt, scheme, alpha, beta, x, s->cell[i], t, P, xn, &Kn, tn, Pn, &nf);
         near[i] = (uint8_t)nf;
         if (!alive) {
             key[i] = ORC_LOST;
@@ -698,6 +758,22 @@ void orc_advect_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, 
         (void)np;
         key[i] = (uint32_t)Kn;
     }
+}
+
+void orc_advect_odes(const orc_mesh *m, const double *U, int64_t nn, double dt, int scheme, double alpha, double beta,
+                     int damage_prop, int deform_prop, orc_store *s, uint32_t *key, uint8_t *near)
+{
+    orc_field f = {U, NULL, nn, 1.0};
+    advect_odes_all(m, &f, 0.0, dt, scheme, alpha, beta, damage_prop, deform_prop, s, key, near);
+}
+
+/* orc_advect_odes in a field that changes in time (as orc_advect_t) */
+void orc_advect_odes_t(const orc_mesh *m, const double *U0, const double *U1, int64_t nn, double dt_u, double since,
+                       double dt, int scheme, double alpha, double beta, int damage_prop, int deform_prop,
+                       orc_store *s, uint32_t *key, uint8_t *near)
+{
+    orc_field f = {U0, U1, nn, dt_u};
+    advect_odes_all(m, &f, since, dt, scheme, alpha, beta, damage_prop, deform_prop, s, key, near);
 }
 
 /*

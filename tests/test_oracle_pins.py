@@ -707,3 +707,124 @@ def test_property_odes_linear_field_closed_forms(dim, scheme):
     # the wrong product order or a transposed gradient would give these instead
     assert np.abs(F0 @ Rn - F_exp).max() > 1e-6
     assert np.abs(np.linalg.matrix_power(_rk_polynomial(A.T * dt, scheme), steps) @ F0 - F_exp).max() > 1e-6
+
+
+# ----------------------------------------------------------------------------
+# field that changes in time (Sec. 2.3): linear interpolation between u^n and
+# u^{n+1}, particle steps that sub-divide the field step
+# ----------------------------------------------------------------------------
+def _time_field_setup(dim, seed):
+    rng = np.random.default_rng(seed)
+    n = 8
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    om = O.OracleMesh.uniform(mesh)
+    nodes = I.uniform_q2_nodes(mesh)
+    counts = np.zeros(mesh.n_cells, np.int32)
+    centre = sum((n // 2) * n ** a for a in range(dim))
+    counts[centre] = 5
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=seed + 1)
+    return rng, mesh, om, nodes, counts, xr, ids
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("scheme", [1, 2, 4])
+def test_time_interpolated_field_equal_ends_is_the_steady_field(dim, scheme):
+    """u^{n+1} = u^n: the interpolated field is u^n itself at every stage time, so the step equals
+    the steady one bit for bit wherever it starts in the field step."""
+    _, mesh, om, nodes, counts, xr, ids = _time_field_setup(dim, 2700 + dim)
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(dim, seed=2705).velocity, nodes))
+    a = O.seed(om, counts, xr, ids, 0)
+    b = O.seed(om, counts, xr, ids, 0)
+    ka, _ = O.advect(om, U, 0.05, scheme, a)
+    kb, _ = O.advect(om, U, 0.05, scheme, b, U1=U.copy(), dt_u=0.3, since=0.17)
+    assert np.array_equal(ka, kb) and np.array_equal(a.x, b.x) and np.array_equal(a.xr, b.xr)
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 4])
+def test_time_interpolated_constant_fields_closed_form(scheme):
+    """u^n = a and u^{n+1} = b constant in space: u~ = a + (t/dt_u)(b - a) depends on time only, so the
+    midpoint rule (RK2) and Simpson's rule (RK4) integrate it exactly over every sub-step, through
+    the end of the field step and beyond it (extrapolation); Euler takes the left end of each
+    sub-step.  Checks the stage times and the time each sub-step starts at."""
+    dim = 3
+    _, mesh, om, nodes, counts, xr, ids = _time_field_setup(dim, 2720)
+    a = np.array([0.11, -0.07, 0.05])
+    b = np.array([-0.05, 0.13, 0.02])
+    U0 = np.repeat(a[:, None], nodes.shape[1], axis=1)
+    U1 = np.repeat(b[:, None], nodes.shape[1], axis=1)
+    st = O.seed(om, counts, xr, ids, 0)
+    m = st.n
+    x0 = st.x[:, :m].copy()
+    dt_u, steps = 0.4, 6
+    h = dt_u / 4                                     # four sub-steps per field step, then two beyond
+    since = 0.0
+    for _ in range(steps):
+        key, _ = O.advect(om, U0, h, scheme, st, U1=U1, dt_u=dt_u, since=since)
+        assert np.all(key != O.LOST)
+        st.cell[:m] = key.astype(np.int32)
+        since += h
+    T = steps * h
+    if scheme == 1:
+        drift = sum(h * (a + (j * h / dt_u) * (b - a)) for j in range(steps))
+    else:
+        drift = a * T + (b - a) * T * T / (2 * dt_u)
+    assert np.abs(st.x[:, :m] - (x0 + drift[:, None])).max() < 1e-15
+    # the steady field u^n would give x0 + a T instead
+    assert np.abs(drift - a * T).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("scheme", [1, 2, 4])
+def test_time_interpolated_linear_field_convergence_order(dim, scheme):
+    """u^n = A (x - c), u^{n+1} = kappa A (x - c) (exact in Q2): u~ = alpha(t) A (x - c) with
+    alpha(t) = 1 + (kappa - 1) t / dt_u, whose exact flow is x(T) = c + expm(A s(T)) (x0 - c),
+    s(T) = T + (kappa - 1) T^2 / (2 dt_u).  The property equations see grad u~ = alpha(t) A:
+    F(T) = expm(A s(T)) F0 and d' = alpha_d alpha(t) |sym A|_F - beta d in closed form.  The error at
+    T (beyond the field step: extrapolation) must fall with the scheme's order as the sub-steps
+    shrink; a wrong stage time lowers the order (RK4 with every stage at the midpoint time is
+    second order here)."""
+    from scipy.linalg import expm
+    rng, mesh, om, nodes, counts, xr, ids = _time_field_setup(dim, 2740 + dim)
+    A = rng.uniform(-1.0, 1.0, (dim, dim))
+    c = np.full(dim, 0.5)
+    U0 = A @ (nodes - c[:, None])
+    kappa, dt_u, T = 2.0, 0.4, 0.6
+    U1 = kappa * U0
+    alpha_d, beta, d0 = 0.7, 1.3, 0.3
+    F0 = rng.uniform(-1.0, 1.0, (dim, dim)) + 2.0 * np.eye(dim)
+    npr = 1 + dim * dim
+    s_T = T + (kappa - 1.0) * T * T / (2.0 * dt_u)
+    E = expm(A * s_T)
+    S = 0.5 * (A + A.T)
+    nS = np.sqrt((S * S).sum())
+    eb = math.exp(-beta * T)
+    d_exact = eb * d0 + alpha_d * nS * ((1 - eb) / beta + (kappa - 1.0) / dt_u * (T / beta - (1 - eb) / beta ** 2))
+    errs = []
+    for m_steps in (6, 12, 24):
+        st = O.seed(om, counts, xr, ids, npr)
+        m = st.n
+        st.prop[0, :m] = d0
+        st.prop[1:npr, :m] = F0.reshape(-1)[:, None]
+        x0 = st.x[:, :m].copy()
+        h = T / m_steps
+        since = 0.0
+        for _ in range(m_steps):
+            key, _ = O.advect_odes(om, U0, h, scheme, st, alpha_d, beta, 0, 1, U1=U1, dt_u=dt_u, since=since)
+            assert np.all(key != O.LOST)
+            st.cell[:m] = key.astype(np.int32)
+            since += h
+        ex = np.abs(st.x[:, :m] - (c[:, None] + E @ (x0 - c[:, None]))).max()
+        eF = np.abs(st.prop[1:npr, :m].T.reshape(m, dim, dim) - (E @ F0)[None]).max()
+        ed = np.abs(st.prop[0, :m] - d_exact).max()
+        errs.append((ex, eF, ed))
+        # the positions alone (no property equations) take the same path
+        st2 = O.seed(om, counts, xr, ids, 0)
+        since = 0.0
+        for _ in range(m_steps):
+            key, _ = O.advect(om, U0, h, scheme, st2, U1=U1, dt_u=dt_u, since=since)
+            st2.cell[: st2.n] = key.astype(np.int32)
+            since += h
+        assert np.array_equal(st2.x[:, : st2.n], st.x[:, :m])
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert np.all(orders > scheme - 0.3) and np.all(orders < scheme + 0.6), orders
