@@ -145,6 +145,30 @@ PIC_API pic_status pic_q2_nodes(pic_ctx *ctx, double *xyz, uint8_t *is_hanging);
  * value is NaN or infinite. */
 PIC_API pic_status pic_set_velocity(pic_ctx *ctx, const void *U, int prec);
 
+/* ---- field that changes in time (Sec. 2.3) ------------------------------ */
+/* The field is known at the ends of a field step [t^n, t^n + dt_u]: u^n (set
+ * by pic_set_velocity) and u^{n+1} (U1, same layout and precision rules as
+ * pic_set_velocity, copied by the library).  Every stage of pic_advance then
+ * evaluates both fields at its point and combines them linearly in time,
+ *   u~(x, t) = u^n(x) + theta (u^{n+1}(x) - u^n(x)),  theta = (t - t^n) / dt_u,
+ * at the stage's time (the step's start, midpoint or end); theta > 1
+ * extrapolates.  Particle steps may sub-divide the field step (dt < dt_u):
+ * the library keeps the time elapsed since t^n in device memory, starts it at
+ * 0 here and advances it by dt with every step (graph replays included).
+ * U1 = NULL switches back to the steady field u^n.  PIC_ESTATE without u^n;
+ * PIC_EINVAL for dt_u not finite and positive; PIC_ENONFINITE as
+ * pic_set_velocity.  A new mesh or mesh displacement switches it off.  Not
+ * available in batches or for the adjoint (PIC_EINVAL there). */
+PIC_API pic_status pic_set_velocity_end(pic_ctx *ctx, const void *U1, int prec, double dt_u);
+/* Next field step: u^{n+1} becomes u^n, U_next becomes u^{n+1}, dt_u the new
+ * field step, the elapsed time restarts at 0.  Needs an end field
+ * (PIC_ESTATE).  If U_next is rejected the old end field stays as the steady
+ * field and time interpolation is off. */
+PIC_API pic_status pic_shift_velocity(pic_ctx *ctx, const void *U_next, int prec, double dt_u);
+/* Set / read the time elapsed since t^n (host double; needs an end field). */
+PIC_API pic_status pic_set_field_time(pic_ctx *ctx, double tau);
+PIC_API pic_status pic_field_time(pic_ctx *ctx, double *tau);
+
 /* ---- store ------------------------------------------------------------ */
 /* Bytes of device scratch a store of `capacity` particles needs. */
 PIC_API pic_status pic_scratch_bytes(pic_ctx *ctx, int64_t capacity, int64_t *bytes);

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 EXPORTS = [
     "pic_create", "pic_set_stream", "pic_destroy", "pic_last_error",
     "pic_mesh_uniform", "pic_mesh_displace", "pic_mesh_octree", "pic_mesh_info", "pic_q2_nodes",
-    "pic_set_velocity", "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
+    "pic_set_velocity", "pic_set_velocity_end", "pic_shift_velocity", "pic_set_field_time", "pic_field_time",
+    "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
     "pic_seed_reference", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
     "pic_interpolate",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
@@ -93,6 +94,10 @@ def load(path: str | None = None):
             "pic_seed_positions": (S, [P, P, P, I64, I32, P]),
             "pic_advance": (S, [P, D, I32, I32, I32]),
             "pic_set_property_odes": (S, [P, I32, I32, C.c_double, C.c_double]),
+            "pic_set_velocity_end": (S, [P, P, I32, C.c_double]),
+            "pic_shift_velocity": (S, [P, P, I32, C.c_double]),
+            "pic_set_field_time": (S, [P, C.c_double]),
+            "pic_field_time": (S, [P, P]),
             "pic_population": (S, [P, I32, I32, U64, U64]),
             "pic_interpolate": (S, [P, I32, P, P, P]),
             "pic_adjoint_workspace_bytes": (S, [P, I32, I32, P]),

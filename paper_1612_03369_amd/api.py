@@ -120,6 +120,37 @@ class Problem:
         prec = L.PIC_F64 if t.dtype == torch.float64 else L.PIC_F32
         self._chk(self.lib.pic_set_velocity(self.h, _ptr(t), prec))
 
+    def _field_tensor(self, U):
+        torch = _torch()
+        t = torch.as_tensor(U).to(self.device).contiguous()
+        if t.dtype not in (torch.float64, torch.float32):
+            t = t.to(torch.float64)
+        if tuple(t.shape) != (self.dim, self.n_nodes):
+            raise ValueError(f"U must have shape ({self.dim}, {self.n_nodes})")
+        return t, (L.PIC_F64 if t.dtype == torch.float64 else L.PIC_F32)
+
+    def set_velocity_end(self, U1, dt_u):
+        """Field u^{n+1} at the end of the field step of length dt_u (Sec. 2.3): stages then use the
+        field interpolated linearly in time; the elapsed time restarts at 0.  U1=None: steady field."""
+        if U1 is None:
+            self._chk(self.lib.pic_set_velocity_end(self.h, None, L.PIC_F64, 1.0))
+            return
+        t, prec = self._field_tensor(U1)
+        self._chk(self.lib.pic_set_velocity_end(self.h, _ptr(t), prec, float(dt_u)))
+
+    def shift_velocity(self, U_next, dt_u):
+        """Next field step: the end field becomes the start field, U_next the end field."""
+        t, prec = self._field_tensor(U_next)
+        self._chk(self.lib.pic_shift_velocity(self.h, _ptr(t), prec, float(dt_u)))
+
+    def set_field_time(self, tau):
+        self._chk(self.lib.pic_set_field_time(self.h, float(tau)))
+
+    def field_time(self) -> float:
+        v = C.c_double()
+        self._chk(self.lib.pic_field_time(self.h, C.byref(v)))
+        return v.value
+
     # ----------------------------------------------------------------- store
     def allocate(self, capacity: int, n_prop: int = 0, prop_dtype="float64"):
         torch = _torch()

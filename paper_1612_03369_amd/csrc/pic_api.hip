@@ -45,6 +45,10 @@ struct pic_ctx {
     // field
     void *u64 = nullptr, *u32 = nullptr;
     bool have_field = false;
+    // field at the end of the field step (time interpolation) and the time
+    // elapsed since its start (one double in device memory)
+    void *u1_64 = nullptr, *u1_32 = nullptr;
+    double *d_tau = nullptr;
     // store
     bool bound = false;
     pic_store store{};
@@ -179,7 +183,10 @@ void free_mesh(pic_ctx *c)
     c->mesh_allocs.clear();
     if (c->u64) hipFree(c->u64);
     if (c->u32) hipFree(c->u32);
-    c->u64 = c->u32 = nullptr;
+    if (c->u1_64) hipFree(c->u1_64);
+    if (c->u1_32) hipFree(c->u1_32);
+    c->u64 = c->u32 = c->u1_64 = c->u1_32 = nullptr;
+    c->h_prob.ti = 0;
     c->have_mesh = false;
     c->node_xyz.clear();
     c->node_hanging.clear();
@@ -243,6 +250,11 @@ pic_status upload_problem(pic_ctx *c)
         pic_status s = dalloc(c, &c->d_prob, 1);
         if (s) return s;
     }
+    if (c->bound) {
+        // the current-buffer index is device state (kernels flip it): keep it
+        HIPCHK(c, hipMemcpyAsync(&c->h_prob.cur, &c->d_prob->cur, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     HIPCHK(c, hipMemcpyAsync(c->d_prob, &c->h_prob, sizeof(ProblemDev), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
@@ -251,33 +263,6 @@ pic_status upload_problem(pic_ctx *c)
 #ifndef PIC_USE_BLOCK_ADVECT
 #define PIC_USE_BLOCK_ADVECT 1
 #endif
-// Cell-block shapes of the LDS-staged advect (uniform meshes) per (dim, precision).
-#ifndef PIC_BLK3_F32
-#define PIC_BLK3_F32 4, 4, 4
-#endif
-constexpr int BLK3_F32[3] = {PIC_BLK3_F32};
-constexpr int BLK3_F64[3] = {4, 4, 4};
-constexpr int BLK2[3] = {8, 8, 1};
-// Cell blocks of the reverse step: smaller in 3D, so that its two LDS windows
-// (field and dU accumulators, double precision) leave room for two workgroups
-// per CU.
-constexpr int ADJ3[3] = {4, 2, 2};
-constexpr int ADJ2[3] = {8, 8, 1};
-inline const int *block_shape(int dim, int prec)
-{
-    return dim == 2 ? BLK2 : (prec == PIC_F32 ? BLK3_F32 : BLK3_F64);
-}
-
-// Candidate cell-block shapes of the batched (double-precision) advect, one
-// of which pic_batch_tune picks per (dim, scheme) group; shape 0 is the
-// default above.
-constexpr int N_SHAPES = 3;
-constexpr int SHAPES2[N_SHAPES][3] = {{8, 8, 1}, {8, 4, 1}, {16, 8, 1}};
-constexpr int SHAPES3[N_SHAPES][3] = {{4, 4, 4}, {4, 2, 2}, {4, 4, 2}};
-static_assert(SHAPES2[0][0] == BLK2[0] && SHAPES2[0][1] == BLK2[1], "shape 0 is the default");
-static_assert(SHAPES3[0][0] == BLK3_F64[0] && SHAPES3[0][1] == BLK3_F64[1] && SHAPES3[0][2] == BLK3_F64[2],
-              "shape 0 is the default");
-inline const int *batch_shape(int dim, int variant) { return dim == 2 ? SHAPES2[variant] : SHAPES3[variant]; }
 
 std::vector<BlockItem> block_items_shape(const MeshDev &m, const int *b, int problem)
 {
@@ -358,43 +343,6 @@ pic_status build_work(pic_ctx *c)
 // ---------------------------------------------------------------------------
 // kernel dispatch over (dim, scheme, precision, mesh kind)
 // ---------------------------------------------------------------------------
-using AdvectFn = void (*)(const ProblemDev *, const WorkItem *, int);
-#ifndef PIC_OCT_LDS
-#define PIC_OCT_LDS 1       // octree advect with the tile's leaf nodes staged in LDS
-#endif
-
-template <int D, int S, typename T, bool O> AdvectFn advect_for_kind(int kind)
-{
-    switch (kind) {
-    case MESH_UNIFORM: return k_advect<D, S, T, MESH_UNIFORM, O>;
-    case MESH_DISPLACED: return k_advect<D, S, T, MESH_DISPLACED, O>;
-    default:
-        if constexpr (D == 3) {
-            if constexpr (O) return k_advect<D, S, T, MESH_OCTREE, true>;
-            else return PIC_OCT_LDS ? k_advect_oct<S, T> : k_advect<D, S, T, MESH_OCTREE>;
-        }
-        return nullptr;
-    }
-}
-template <int D, int S, bool O> AdvectFn advect_for_prec(int prec, int kind)
-{
-    return prec == PIC_F32 ? advect_for_kind<D, S, float, O>(kind) : advect_for_kind<D, S, double, O>(kind);
-}
-template <int D, bool O> AdvectFn advect_for_scheme(int scheme, int prec, int kind)
-{
-    switch (scheme) {
-    case PIC_EULER: return advect_for_prec<D, 1, O>(prec, kind);
-    case PIC_RK2: return advect_for_prec<D, 2, O>(prec, kind);
-    case PIC_RK4: return advect_for_prec<D, 4, O>(prec, kind);
-    }
-    return nullptr;
-}
-AdvectFn advect_kernel(int dim, int scheme, int prec, int kind, bool ode = false)
-{
-    if (ode) return dim == 2 ? advect_for_scheme<2, true>(scheme, prec, kind) : advect_for_scheme<3, true>(scheme, prec, kind);
-    return dim == 2 ? advect_for_scheme<2, false>(scheme, prec, kind) : advect_for_scheme<3, false>(scheme, prec, kind);
-}
-
 pic_status require_ready(pic_ctx *c, bool field)
 {
     if (!c) return PIC_EINVAL;
@@ -439,59 +387,6 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
     return PIC_OK;
 }
 
-using BlockFn = void (*)(const ProblemDev *, const BlockItem *, int);
-template <int D, int S, bool F, bool O> BlockFn block_for_prec(int prec)
-{
-    if constexpr (D == 3) {
-        if (prec == PIC_F32) return k_advect_blk<3, S, float, BLK3_F32[0], BLK3_F32[1], BLK3_F32[2], F, O>;
-        return k_advect_blk<3, S, double, BLK3_F64[0], BLK3_F64[1], BLK3_F64[2], F, O>;
-    } else {
-        if (prec == PIC_F32) return k_advect_blk<2, S, float, BLK2[0], BLK2[1], 1, F, O>;
-        return k_advect_blk<2, S, double, BLK2[0], BLK2[1], 1, F, O>;
-    }
-}
-template <int D, bool F, bool O> BlockFn block_for_scheme(int scheme, int prec)
-{
-    switch (scheme) {
-    case PIC_EULER: return block_for_prec<D, 1, F, O>(prec);
-    case PIC_RK2: return block_for_prec<D, 2, F, O>(prec);
-    case PIC_RK4: return block_for_prec<D, 4, F, O>(prec);
-    }
-    return nullptr;
-}
-// Double-precision, unfused block advect of cell-block shape `variant` (batch).
-template <int D, int S, int V> BlockFn shape_kernel()
-{
-    if constexpr (D == 3) return k_advect_blk<3, S, double, SHAPES3[V][0], SHAPES3[V][1], SHAPES3[V][2], false>;
-    else return k_advect_blk<2, S, double, SHAPES2[V][0], SHAPES2[V][1], 1, false>;
-}
-template <int D, int S> BlockFn shape_kernel_v(int variant)
-{
-    switch (variant) {
-    case 0: return shape_kernel<D, S, 0>();
-    case 1: return shape_kernel<D, S, 1>();
-    case 2: return shape_kernel<D, S, 2>();
-    }
-    return nullptr;
-}
-BlockFn batch_block_kernel(int dim, int scheme, int variant)
-{
-    const int S = scheme == PIC_EULER ? 1 : scheme == PIC_RK2 ? 2 : 4;
-    if (dim == 2) return S == 1 ? shape_kernel_v<2, 1>(variant) : S == 2 ? shape_kernel_v<2, 2>(variant) : shape_kernel_v<2, 4>(variant);
-    return S == 1 ? shape_kernel_v<3, 1>(variant) : S == 2 ? shape_kernel_v<3, 2>(variant) : shape_kernel_v<3, 4>(variant);
-}
-
-// ode: with the property equations (the problem's odes flag)
-BlockFn block_kernel(int dim, int scheme, int prec, bool fused, bool ode = false)
-{
-    if (ode) {
-        if (dim == 2) return fused ? block_for_scheme<2, true, true>(scheme, prec) : block_for_scheme<2, false, true>(scheme, prec);
-        return fused ? block_for_scheme<3, true, true>(scheme, prec) : block_for_scheme<3, false, true>(scheme, prec);
-    }
-    if (dim == 2) return fused ? block_for_scheme<2, true, false>(scheme, prec) : block_for_scheme<2, false, false>(scheme, prec);
-    return fused ? block_for_scheme<3, true, false>(scheme, prec) : block_for_scheme<3, false, false>(scheme, prec);
-}
-
 #ifndef PIC_FUSE_STEPS
 #define PIC_FUSE_STEPS 1
 #endif
@@ -502,8 +397,9 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
 {
     const int pr = prec == PIC_F32;
     const bool ode = dp == c->d_prob && c->h_prob.odes != 0;
-    BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false, ode);
-    BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true, ode);
+    const bool ti = dp == c->d_prob && c->h_prob.ti != 0;
+    BlockFn fa = block_kernel(c->mesh.dim, scheme, prec, false, ode, ti);
+    BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true, ode, ti);
     LAUNCH(c, "advect", fa, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0);
@@ -519,14 +415,15 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
 pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)
 {
     const bool ode = dp == c->d_prob && c->h_prob.odes != 0;
+    const bool ti = dp == c->d_prob && c->h_prob.ti != 0;
     if (PIC_USE_BLOCK_ADVECT && c->mesh.kind == MESH_UNIFORM && c->n_blk[prec == PIC_F32]) {
-        BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false, ode);
+        BlockFn f = block_kernel(c->mesh.dim, scheme, prec, false, ode, ti);
         const int pr = prec == PIC_F32;
         LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr],
                c->n_blk[pr]);
         return enqueue_sort(c, dp, 1);
     }
-    AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind, ode);
+    AdvectFn f = advect_kernel(c->mesh.dim, scheme, prec, c->mesh.kind, ode, ti);
     if (!f) return fail(c, PIC_EINVAL, "unsupported combination dim=%d scheme=%d kind=%d", c->mesh.dim, scheme, c->mesh.kind);
     LAUNCH(c, "advect", f, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
     return enqueue_sort(c, dp, 1);
@@ -565,7 +462,7 @@ extern "C" void pic_destroy(pic_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     free_mesh(c);
-    for (void *p : {c->u64, c->u32, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
+    for (void *p : {c->u64, c->u32, c->u1_64, c->u1_32, (void *)c->d_tau, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
                     (void *)c->d_rc, (void *)c->d_blk[0], (void *)c->d_blk[1], (void *)c->d_blk_adj})
         if (p) hipFree(p);
     for (auto &p : c->pending) {
@@ -670,6 +567,7 @@ extern "C" pic_status pic_mesh_displace(pic_ctx *c, const double *vertices)
             }
         }
     }
+    c->h_prob.ti = 0;                    // both fields must be set again on the new geometry
     if (c->bound) {
         c->h_prob.mesh = m;
         s = upload_problem(c);
@@ -706,43 +604,123 @@ extern "C" pic_status pic_q2_nodes(pic_ctx *c, double *xyz, uint8_t *is_hanging)
 // ===========================================================================
 // field
 // ===========================================================================
-extern "C" pic_status pic_set_velocity(pic_ctx *c, const void *U, int prec)
+namespace {
+// Repack U (device [dim][n_nodes], prec) into the node-major arrays d64 / d32
+// (allocated on first use), reject non-finite values, resolve hanging nodes.
+pic_status load_field(pic_ctx *c, const void *U, int prec, void **d64, void **d32)
 {
-    if (!c) return PIC_EINVAL;
-    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
     if (!U) return fail(c, PIC_EINVAL, "null field");
     if (prec != PIC_F64 && prec != PIC_F32) return fail(c, PIC_EINVAL, "bad precision");
     hipSetDevice(c->device);
     const int d = c->mesh.dim;
     const int64_t nn = c->mesh.n_nodes;
     const size_t w = d == 3 ? 4 : 2;
-    if (!c->u64) {
-        pic_status s;
-        if ((s = dalloc(c, (double **)&c->u64, w * (size_t)nn))) return s;
-        if ((s = dalloc(c, (float **)&c->u32, w * (size_t)nn))) return s;
-    }
+    pic_status s;
+    if (!*d64 && (s = dalloc(c, (double **)d64, w * (size_t)nn))) return s;
+    if (!*d32 && (s = dalloc(c, (float **)d32, w * (size_t)nn))) return s;
     int *flag = nullptr;
-    pic_status s = dalloc(c, &flag, 1);
+    s = dalloc(c, &flag, 1);
     if (s) return s;
     HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
     unsigned grid = (unsigned)((nn + BLOCK - 1) / BLOCK);
     if (d == 3)
-        hipLaunchKernelGGL(k_repack_field<3>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, c->u64, c->u32, flag);
+        hipLaunchKernelGGL(k_repack_field<3>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, flag);
     else
-        hipLaunchKernelGGL(k_repack_field<2>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, c->u64, c->u32, flag);
+        hipLaunchKernelGGL(k_repack_field<2>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, flag);
     int hflag = 0;
     HIPCHK(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     hipFree(flag);
     if (hflag) return fail(c, PIC_ENONFINITE, "velocity has NaN or infinite values");
-    if (c->mesh.kind == MESH_OCTREE) {
-        s = resolve_hanging(c);
+    if (c->mesh.kind == MESH_OCTREE) return resolve_hanging(c, *d64, *d32);
+    return PIC_OK;
+}
+
+pic_status set_field_time(pic_ctx *c, double tau)
+{
+    if (!c->d_tau) {
+        pic_status s = dalloc(c, &c->d_tau, 1);
         if (s) return s;
     }
-    c->have_field = true;
+    HIPCHK(c, hipMemcpyAsync(c->d_tau, &tau, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+pic_status publish_fields(pic_ctx *c)
+{
     c->h_prob.u64 = c->u64;
     c->h_prob.u32 = c->u32;
+    c->h_prob.u1_64 = c->u1_64;
+    c->h_prob.u1_32 = c->u1_32;
+    c->h_prob.tau = c->d_tau;
     if (c->bound) return upload_problem(c);
+    return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_set_velocity(pic_ctx *c, const void *U, int prec)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_mesh) return fail(c, PIC_ESTATE, "no mesh");
+    pic_status s = load_field(c, U, prec, &c->u64, &c->u32);
+    if (s) return s;
+    c->have_field = true;
+    return publish_fields(c);
+}
+
+extern "C" pic_status pic_set_velocity_end(pic_ctx *c, const void *U1, int prec, double dt_u)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_field) return fail(c, PIC_ESTATE, "set the field at the start of the field step first");
+    if (!U1) {
+        c->h_prob.ti = 0;
+        return publish_fields(c);
+    }
+    if (!(std::isfinite(dt_u) && dt_u > 0.0)) return fail(c, PIC_EINVAL, "dt_u must be finite and positive");
+    pic_status s = load_field(c, U1, prec, &c->u1_64, &c->u1_32);
+    if (s) return s;
+    if ((s = set_field_time(c, 0.0))) return s;
+    c->h_prob.ti = 1;
+    c->h_prob.dt_u = dt_u;
+    return publish_fields(c);
+}
+
+extern "C" pic_status pic_shift_velocity(pic_ctx *c, const void *U_next, int prec, double dt_u)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->have_field || !c->h_prob.ti) return fail(c, PIC_ESTATE, "no field at the end of the field step");
+    if (!(std::isfinite(dt_u) && dt_u > 0.0)) return fail(c, PIC_EINVAL, "dt_u must be finite and positive");
+    if (!U_next) return fail(c, PIC_EINVAL, "null field");
+    // the end field becomes the start field; U_next is loaded over the old start
+    std::swap(c->u64, c->u1_64);
+    std::swap(c->u32, c->u1_32);
+    pic_status s = load_field(c, U_next, prec, &c->u1_64, &c->u1_32);
+    if (s) {
+        // keep a consistent pair: the previous end field is still the start field
+        c->h_prob.ti = 0;
+        publish_fields(c);
+        return s;
+    }
+    if ((s = set_field_time(c, 0.0))) return s;
+    c->h_prob.dt_u = dt_u;
+    return publish_fields(c);
+}
+
+extern "C" pic_status pic_set_field_time(pic_ctx *c, double tau)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->h_prob.ti) return fail(c, PIC_ESTATE, "no field at the end of the field step");
+    if (!std::isfinite(tau)) return fail(c, PIC_EINVAL, "time must be finite");
+    return set_field_time(c, tau);
+}
+
+extern "C" pic_status pic_field_time(pic_ctx *c, double *tau)
+{
+    if (!c || !tau) return PIC_EINVAL;
+    if (!c->h_prob.ti) return fail(c, PIC_ESTATE, "no field at the end of the field step");
+    HIPCHK(c, hipMemcpyAsync(tau, c->d_tau, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
 
@@ -771,9 +749,12 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     int64_t need = (int64_t)scratch_layout(s->capacity, c->mesh.n_cells, nullptr, nullptr);
     if (!s->scratch || s->scratch_bytes < need) return fail(c, PIC_EINVAL, "scratch too small: need %lld bytes", (long long)need);
     hipSetDevice(c->device);
+    c->bound = false;                    // a new store starts in buffer A
     c->store = *s;
     scratch_layout(s->capacity, c->mesh.n_cells, (char *)s->scratch, &c->scr);
     ProblemDev &P = c->h_prob;
+    const int ti = P.ti;                 // the field pair belongs to the mesh, not the store
+    const double dt_u = P.dt_u;
     P = ProblemDev{};
     P.mesh = c->mesh;
     for (int b = 0; b < 2; ++b)
@@ -786,6 +767,11 @@ extern "C" pic_status pic_bind_store(pic_ctx *c, const pic_store *s)
     P.dt = 0.0;
     P.u64 = c->u64;
     P.u32 = c->u32;
+    P.ti = ti;
+    P.dt_u = dt_u;
+    P.u1_64 = c->u1_64;
+    P.u1_32 = c->u1_32;
+    P.tau = c->d_tau;
     P.scr = c->scr;
     c->last_dt = 0.0;
     // zeroed state: empty buffers, zero counters

@@ -21,6 +21,14 @@ struct ProblemDev {
     double dt;
     const void *u64;         // repacked field, double
     const void *u32;         // repacked field, float
+    // field that changes in time (Sec. 2.3; off unless ti != 0): u^{n+1}
+    // repacked as u1_64 / u1_32, the field step dt_u, and the time elapsed
+    // since t^n in *tau (device memory, advanced by dt on every counted step)
+    int ti;
+    double dt_u;
+    const void *u1_64;
+    const void *u1_32;
+    double *tau;
     ScratchDev scr;
     // adjoint: arrays of the segment being replayed
     const double *adj_lam_in;  // [dim][cap] lambda of the next step, in that step's order

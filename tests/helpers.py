@@ -27,18 +27,23 @@ def oracle_store(cfg, n_prop=None, mesh=None, cap=None):
     return om, st
 
 
-def oracle_run_tracking(om, U, dt, scheme, steps, st, odes=None):
+def oracle_run_tracking(om, U, dt, scheme, steps, st, odes=None, tfield=None):
     """Run the oracle step by step; return ids that were near a face at any step.
-    odes = (alpha, beta, damage_prop, deform_prop) integrates the property equations too."""
+    odes = (alpha, beta, damage_prop, deform_prop) integrates the property equations too.
+    tfield = dict(U1=..., dt_u=..., since=...): the field changes in time (U at t^n, U1 at
+    t^n + dt_u); tfield["since"] is advanced by dt after every step."""
     near_ids = set()
     lost = 0
     for _ in range(steps):
         n = st.n
         ids_before = st.id[:n].copy()
+        tf = {} if tfield is None else dict(U1=tfield["U1"], dt_u=tfield["dt_u"], since=tfield["since"])
         if odes is None:
-            key, near = O.advect(om, U, dt, scheme, st)
+            key, near = O.advect(om, U, dt, scheme, st, **tf)
         else:
-            key, near = O.advect_odes(om, U, dt, scheme, st, *odes)
+            key, near = O.advect_odes(om, U, dt, scheme, st, *odes, **tf)
+        if tfield is not None:
+            tfield["since"] = tfield["since"] + dt
         near_ids |= set(ids_before[near.astype(bool)].tolist())
         lost += int((key == O.LOST).sum())
         perm, cs = O.stable_sort_perm(om.n_cells, st.cell[:n], key)
