@@ -80,6 +80,12 @@ def lib():
             L.orc_advect_odes_t.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int,
                                             C.c_double, C.c_double, C.c_int, C.c_int, P, P, P]
             L.orc_advect_odes_t.restype = None
+            L.orc_cell_mean.argtypes = [C.c_int64, P, P, C.c_int, P, P]
+            L.orc_cell_mean.restype = None
+            L.orc_interp_points.argtypes = [P, P, P, C.c_int, C.c_int, P, P]
+            L.orc_interp_points.restype = None
+            L.orc_seed_mh.argtypes = [P, P, P, C.c_int, C.c_uint64, C.c_uint32, P, P]
+            L.orc_seed_mh.restype = C.c_int
             L.orc_sort_perm.argtypes = [C.c_int64, C.c_int64, P, P, P, P]
             L.orc_step.restype = C.c_int
             L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, P, P, P]
@@ -413,6 +419,46 @@ def cell_average(n_cells, st: OracleStore):
     cs = np.ascontiguousarray(st.cell_start, np.int64)
     lib().orc_cell_average(int(n_cells), _p(cs), C.byref(st.c), _p(out), _p(cnt))
     return out[:, : st.n_prop], cnt
+
+
+def cell_mean(n_cells, st: OracleStore, mode):
+    """Geometric (mode 1) or harmonic (mode 2) mean of each property per cell (Sec. 2.7 (ii))."""
+    out = np.zeros((n_cells, max(st.n_prop, 1)))
+    cnt = np.zeros(n_cells, np.int32)
+    cs = np.ascontiguousarray(st.cell_start, np.int64)
+    lib().orc_cell_mean(int(n_cells), _p(cs), C.byref(st.c), int(mode), _p(out), _p(cnt))
+    return out[:, : st.n_prop], cnt
+
+
+INTERP_NEAREST, INTERP_INV_DISTANCE, INTERP_SHAPE = 0, 1, 2
+
+
+def interp_points(mesh: OracleMesh, st: OracleStore, kind, qhat):
+    """Properties at the evaluation points qhat [dim][n_q] (reference coordinates, every cell) from the
+    particles of the point's cell (Sec. 2.7 (i), (iii), (iv)); returns [n_cells][n_q][n_prop]."""
+    qhat = np.ascontiguousarray(qhat, np.float64)
+    n_q = qhat.shape[1]
+    out = np.zeros((mesh.n_cells, n_q, max(st.n_prop, 1)))
+    cs = np.ascontiguousarray(st.cell_start, np.int64)
+    lib().orc_interp_points(C.byref(mesh.c), _p(cs), C.byref(st.c), int(kind), n_q, _p(qhat), _p(out))
+    return out[:, :, : st.n_prop]
+
+
+def seed_mh(mesh: OracleMesh, counts, rho, J, seed, first_id, n_prop, cap=None):
+    """Metropolis-Hastings generation in the reference cells (Sec. 2.2); returns (store, longest run)."""
+    counts = np.ascontiguousarray(counts, np.int32)
+    rho = np.ascontiguousarray(rho, np.float64)
+    n = int(counts.sum())
+    st = OracleStore(mesh.dim, cap or max(n, 1), n_prop)
+    longest = np.zeros(1, np.int64)
+    rc = lib().orc_seed_mh(C.byref(mesh.c), _p(counts), _p(rho), int(J), int(seed), int(first_id), C.byref(st.c),
+                           _p(longest))
+    if rc != 0:
+        raise ValueError("capacity too small")
+    cs = np.zeros(mesh.n_cells + 1, np.int64)
+    cs[1:] = np.cumsum(counts)
+    st.cell_start = cs
+    return st, int(longest[0])
 
 
 def linear_least_squares(n_cells, dim, cell_start, xr, prop, rcond=1e-10):

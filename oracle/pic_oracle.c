@@ -880,6 +880,82 @@ double orc_uniform01(uint64_t seed, uint64_t step, uint64_t cell, uint64_t slot,
 }
 
 /* ------------------------------------------------------------------ */
+/* Metropolis-Hastings generation (Sec. 2.2)                           */
+/* ------------------------------------------------------------------ */
+/* rho^(xhat) = max(0, rho_h(Phi_K(xhat))) |det grad Phi_K(xhat)|, rho_h the
+ * Q2 interpolant of the nodal density (naive 27-term sum) */
+static double mh_density(const orc_mesh *m, const double *rho, int64_t K, const double *t)
+{
+    int d = m->dim;
+    double r = 0.0;
+    for (int loc = 0; loc < nloc(d); ++loc) r += rho[q2_node(m, K, loc)] * q2_basis(d, loc, t, NULL);
+    double x[3], J[3][3];
+    map_to_real(m, K, t, x, J);
+    double det = d == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                        : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                              J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                              J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    return (r > 0.0 ? r : 0.0) * fabs(det);
+}
+
+/*
+ * For every cell K a Metropolis-Hastings chain in the reference cell with a
+ * proposal uniform in Khat: it starts at the centre of Khat; state i
+ * (i = 0 .. J counts[K] - 1) proposes xhat' with coordinates
+ * uniform01(seed, 1, K, i, axis) and moves there when
+ * uniform01(seed, 2, K, i, 0) * rho^(current) < rho^(xhat'), else repeats the
+ * current state.  States J-1, 2J-1, ... become the cell's particles, stored
+ * cell by cell with ids first_id + store position and properties = initial
+ * position.  *longest_run = the longest run of equal consecutive states over
+ * all chains (J must exceed it for the thinned samples to be distinct).
+ * Returns -1 if the store is too small.
+ */
+int orc_seed_mh(const orc_mesh *m, const int32_t *counts, const double *rho, int J, uint64_t seed,
+                uint32_t first_id, orc_store *s, int64_t *longest_run)
+{
+    int d = m->dim;
+    int64_t nc = orc_n_cells(m), total = 0, longest = 0;
+    for (int64_t K = 0; K < nc; ++K) total += counts[K];
+    if (total > s->cap) return -1;
+    int64_t p = 0;
+    for (int64_t K = 0; K < nc; ++K) {
+        double cur[3] = {0.5, 0.5, 0.5};
+        double rcur = mh_density(m, rho, K, cur);
+        int64_t run = 0;                     /* runs count chain states; the start is not one */
+        int64_t n_states = (int64_t)J * counts[K];
+        for (int64_t i = 0; i < n_states; ++i) {
+            double prop[3] = {0, 0, 0};
+            for (int a = 0; a < d; ++a) prop[a] = orc_uniform01(seed, 1, (uint64_t)K, (uint64_t)i, (uint64_t)a);
+            double rprop = mh_density(m, rho, K, prop);
+            double u = orc_uniform01(seed, 2, (uint64_t)K, (uint64_t)i, 0);
+            if (u * rcur < rprop) {
+                for (int a = 0; a < d; ++a) cur[a] = prop[a];
+                rcur = rprop;
+                run = 1;
+            } else {
+                ++run;
+            }
+            if (run > longest) longest = run;
+            if ((i + 1) % J == 0) {
+                double x[3];
+                map_to_real(m, K, cur, x, NULL);
+                for (int a = 0; a < d; ++a) {
+                    s->x[a * s->cap + p] = x[a];
+                    s->xr[a * s->cap + p] = cur[a];
+                }
+                s->cell[p] = (int32_t)K;
+                s->id[p] = first_id + (uint32_t)p;
+                for (int j = 0; j < s->n_prop; ++j) s->prop[j * s->cap + p] = x[j % d];
+                ++p;
+            }
+        }
+    }
+    s->n = p;
+    *longest_run = longest;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* population management                                               */
 /* ------------------------------------------------------------------ */
 /*
@@ -994,6 +1070,127 @@ void orc_cell_average(int64_t n_cells, const int64_t *cell_start, const orc_stor
             double sum = 0.0;
             for (int64_t i = b; i < e; ++i) sum += s->prop[j * s->cap + i];
             out[K * np + j] = sum / (double)(e - b);
+        }
+    }
+}
+
+/*
+ * Geometric (mode 1) and harmonic (mode 2) averages of each property over the
+ * particles of each cell (Sec. 2.7 (ii)):
+ *   geometric  exp( (1/n) sum_k log p_k )   (0 if a value is 0, NaN if one is negative)
+ *   harmonic   n / sum_k (1 / p_k)          (0 if a value is 0)
+ * Empty cells give NaN.
+ */
+void orc_cell_mean(int64_t n_cells, const int64_t *cell_start, const orc_store *s, int mode,
+                   double *out /* [n_cells][n_prop] */, int32_t *count)
+{
+    int np = s->n_prop;
+    for (int64_t K = 0; K < n_cells; ++K) {
+        int64_t b = cell_start[K], e = cell_start[K + 1];
+        count[K] = (int32_t)(e - b);
+        for (int j = 0; j < np; ++j) {
+            if (e == b) {
+                out[K * np + j] = NAN;
+                continue;
+            }
+            double sum = 0.0;
+            for (int64_t i = b; i < e; ++i) {
+                double v = s->prop[j * s->cap + i];
+                sum += mode == 1 ? log(v) : 1.0 / v;
+            }
+            out[K * np + j] = mode == 1 ? exp(sum / (double)(e - b)) : (double)(e - b) / sum;
+        }
+    }
+}
+
+/*
+ * Particle -> evaluation points of each cell (Sec. 2.7 (i), (iii), (iv)).  The
+ * points are given in reference coordinates qhat [dim][n_q], the same for
+ * every cell; only the particles of the point's own cell take part.
+ *   kind 0, nearest neighbour: the property of the particle with the smallest
+ *           physical distance |Phi_K(qhat) - x_k| (ties: first in store order);
+ *   kind 1, distance weighted: weights 1 / |Phi_K(qhat) - x_k|^2; particles at
+ *           the point itself (distance 0) take the whole weight, equally;
+ *   kind 2, shape-function weighted: weights w_k = sum_v N_v(qhat) N_v(xhat_k)
+ *           over the d-linear vertex shape functions N_v of the reference cell.
+ * out [n_cells][n_q][n_prop]; empty cells give NaN.
+ */
+static double q1_vertex_sum(int dim, const double *a, const double *b)
+{
+    /* sum_v N_v(a) N_v(b), written out as the sum over the 2^dim vertices */
+    double sum = 0.0;
+    for (int v = 0; v < nvert(dim); ++v) {
+        double na = q1_shape(dim, v, a, NULL), nb = q1_shape(dim, v, b, NULL);
+        sum += na * nb;
+    }
+    return sum;
+}
+
+void orc_interp_points(const orc_mesh *m, const int64_t *cell_start, const orc_store *s, int kind, int n_q,
+                       const double *qhat, double *out)
+{
+    int d = m->dim, np = s->n_prop;
+    int64_t nc = orc_n_cells(m);
+    for (int64_t K = 0; K < nc; ++K) {
+        int64_t b = cell_start[K], e = cell_start[K + 1];
+        for (int q = 0; q < n_q; ++q) {
+            double qr[3] = {0, 0, 0}, xq[3], J[3][3];
+            for (int a = 0; a < d; ++a) qr[a] = qhat[a * n_q + q];
+            map_to_real(m, K, qr, xq, J);
+            double *o = out + (K * n_q + q) * np;
+            if (e == b) {
+                for (int j = 0; j < np; ++j) o[j] = NAN;
+                continue;
+            }
+            if (kind == 0) {
+                int64_t best = b;
+                double bd = INFINITY;
+                for (int64_t i = b; i < e; ++i) {
+                    double d2 = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        double r = s->x[a * s->cap + i] - xq[a];
+                        d2 += r * r;
+                    }
+                    if (d2 < bd) {
+                        bd = d2;
+                        best = i;
+                    }
+                }
+                for (int j = 0; j < np; ++j) o[j] = s->prop[j * s->cap + best];
+                continue;
+            }
+            /* weights: distance (with the exact-hit limit) or shape-function products */
+            int n_hit = 0;
+            for (int64_t i = b; i < e && kind == 1; ++i) {
+                double d2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double r = s->x[a * s->cap + i] - xq[a];
+                    d2 += r * r;
+                }
+                n_hit += d2 == 0.0;
+            }
+            for (int j = 0; j < np; ++j) {
+                double sw = 0.0, swp = 0.0;
+                for (int64_t i = b; i < e; ++i) {
+                    double w;
+                    if (kind == 1) {
+                        double d2 = 0.0;
+                        for (int a = 0; a < d; ++a) {
+                            double r = s->x[a * s->cap + i] - xq[a];
+                            d2 += r * r;
+                        }
+                        if (n_hit) w = d2 == 0.0 ? 1.0 : 0.0;
+                        else w = 1.0 / d2;
+                    } else {
+                        double xr[3] = {0, 0, 0};
+                        for (int a = 0; a < d; ++a) xr[a] = s->xr[a * s->cap + i];
+                        w = q1_vertex_sum(d, qr, xr);
+                    }
+                    sw += w;
+                    swp += w * s->prop[j * s->cap + i];
+                }
+                o[j] = swp / sw;
+            }
         }
     }
 }

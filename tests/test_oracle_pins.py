@@ -828,3 +828,205 @@ def test_time_interpolated_linear_field_convergence_order(dim, scheme):
     errs = np.array(errs)
     orders = np.log2(errs[:-1] / errs[1:])
     assert np.all(orders > scheme - 0.3) and np.all(orders < scheme + 0.6), orders
+
+
+# ----------------------------------------------------------------------------
+# particle -> field: geometric/harmonic means, point interpolators (Sec. 2.7)
+# ----------------------------------------------------------------------------
+def _interp_store(dim, n, seed, displaced=False, ppc_hi=7):
+    rng = np.random.default_rng(seed)
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    if displaced:
+        vert = I.displaced_vertices(mesh, 0.2, seed=seed + 1)
+        om = O.OracleMesh.displaced(mesh, vert)
+    else:
+        vert = None
+        om = O.OracleMesh.uniform(mesh)
+    counts = rng.integers(0, ppc_hi, mesh.n_cells).astype(np.int32)
+    counts[0] = 0
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=seed + 2)
+    st = O.seed(om, counts, xr, ids, 3)
+    st.prop[:, : st.n] = rng.uniform(0.5, 2.0, (3, st.n))
+    return mesh, vert, om, st
+
+
+def test_geometric_and_harmonic_means_match_scipy():
+    from scipy.stats import gmean, hmean
+    mesh, _, om, st = _interp_store(2, 5, 2800)
+    cs = st.cell_start
+    g, cnt = O.cell_mean(om.n_cells, st, 1)
+    h, _ = O.cell_mean(om.n_cells, st, 2)
+    for K in range(om.n_cells):
+        b, e = cs[K], cs[K + 1]
+        assert cnt[K] == e - b
+        if e == b:
+            assert np.all(np.isnan(g[K])) and np.all(np.isnan(h[K]))
+            continue
+        for j in range(3):
+            v = st.prop[j, b:e]
+            assert abs(g[K, j] - gmean(v)) <= 1e-14 * gmean(v)
+            assert abs(h[K, j] - hmean(v)) <= 1e-14 * hmean(v)
+            assert h[K, j] <= g[K, j] * (1 + 1e-14) and g[K, j] <= v.mean() * (1 + 1e-14)
+    # a zero value: both means 0; a negative value: geometric mean undefined (NaN)
+    K = int(np.argmax(np.diff(cs)))
+    st.prop[0, cs[K]] = 0.0
+    st.prop[1, cs[K]] = -1.0
+    g, _ = O.cell_mean(om.n_cells, st, 1)
+    h, _ = O.cell_mean(om.n_cells, st, 2)
+    assert g[K, 0] == 0.0 and h[K, 0] == 0.0 and np.isnan(g[K, 1])
+
+
+def _numpy_phys(mesh, vert, K, t):
+    """Phi_K(t) written independently: bi/trilinear blend of the cell's vertices."""
+    dim = mesh.dim
+    ijk = np.unravel_index(K, mesh.n[:dim], order="F")
+    if vert is None:
+        return np.array([mesh.lo[a] + (ijk[a] + t[a]) * mesh.h[a] for a in range(dim)])
+    nv = [mesh.n[a] + 1 for a in range(dim)]
+    x = np.zeros(dim)
+    for corner in np.ndindex(*(2,) * dim):
+        w = np.prod([t[a] if corner[a] else 1 - t[a] for a in range(dim)])
+        vi = np.ravel_multi_index(tuple(ijk[a] + corner[a] for a in range(dim)), nv, order="F")
+        x += w * vert[:, vi]
+    return x
+
+
+@pytest.mark.parametrize("dim,displaced", [(2, False), (3, False), (2, True), (3, True)])
+def test_point_interpolators_against_brute_force(dim, displaced):
+    """Nearest neighbour, inverse-distance and shape-function weights written out in NumPy per cell and
+    point (the shape-function kernel in its product form prod_a[(1-q_a)(1-x_a) + q_a x_a], equal to the
+    oracle's sum over the vertices)."""
+    mesh, vert, om, st = _interp_store(dim, 3, 2810 + dim + 10 * displaced)
+    g = 1 / math.sqrt(3)
+    pts = np.array(list(np.ndindex(*(2,) * dim)), float).T
+    qhat = 0.5 + (pts - 0.5) * g                     # the 2^dim Gauss points
+    qhat = np.concatenate([qhat, np.full((dim, 1), 0.5)], axis=1)
+    cs = st.cell_start
+    res = [O.interp_points(om, st, k, qhat) for k in (O.INTERP_NEAREST, O.INTERP_INV_DISTANCE, O.INTERP_SHAPE)]
+    for K in range(om.n_cells):
+        b, e = cs[K], cs[K + 1]
+        for q in range(qhat.shape[1]):
+            if e == b:
+                assert all(np.all(np.isnan(r[K, q])) for r in res)
+                continue
+            xq = _numpy_phys(mesh, vert, K, qhat[:, q])
+            d2 = ((st.x[:, b:e] - xq[:, None]) ** 2).sum(axis=0)
+            P = st.prop[:, b:e]
+            assert np.array_equal(res[0][K, q], P[:, int(np.argmin(d2))])
+            w = 1 / d2
+            assert np.allclose(res[1][K, q], (P * w).sum(axis=1) / w.sum(), rtol=1e-13, atol=0)
+            ws = np.prod((1 - qhat[:, q, None]) * (1 - st.xr[:, b:e]) + qhat[:, q, None] * st.xr[:, b:e], axis=0)
+            assert np.allclose(res[2][K, q], (P * ws).sum(axis=1) / ws.sum(), rtol=1e-13, atol=0)
+    # a constant property is reproduced by all three; a particle at the point takes the whole weight
+    st.prop[2, : st.n] = 1.25
+    for k in range(3):
+        r = O.interp_points(om, st, k, qhat)
+        ok = ~np.isnan(r[:, :, 2])
+        assert np.all(np.abs(r[:, :, 2][ok] - 1.25) <= 1e-15)
+    K = int(np.argmax(np.diff(cs)))
+    i = cs[K]
+    q1 = st.xr[:dim, i : i + 1].copy()
+    r = O.interp_points(om, st, O.INTERP_INV_DISTANCE, q1)
+    assert np.array_equal(r[K, 0], st.prop[:, i])
+
+
+# ----------------------------------------------------------------------------
+# Metropolis-Hastings generation (Sec. 2.2)
+# ----------------------------------------------------------------------------
+def test_mh_constant_density_takes_every_proposal():
+    """rho^ constant: every proposal is accepted, so the particles are the proposals of states J-1,
+    2J-1, ... drawn from the counter hash, and no state repeats."""
+    mesh = I.UniformMesh(3, (3, 2, 2))
+    om = O.OracleMesh.uniform(mesh)
+    nn = int(np.prod(mesh.node_shape))
+    counts = np.arange(mesh.n_cells, dtype=np.int32) % 4
+    J, seed = 3, 77
+    st, longest = O.seed_mh(om, counts, np.full(nn, 2.5), J, seed, 1000, 1)
+    assert longest == 1
+    p = 0
+    for K in range(mesh.n_cells):
+        for s in range(counts[K]):
+            i = J * (s + 1) - 1
+            t = [O.uniform01(seed, 1, K, i, a) for a in range(3)]
+            assert np.array_equal(st.xr[:, p], t) and st.cell[p] == K and st.id[p] == 1000 + p
+            p += 1
+    assert st.n == p == counts.sum()
+
+
+def _q2_numpy_scalar(rho_cell, t):
+    """Q2 interpolant on [0,1]^2 of 3x3 nodal values (numpy, Lagrange product form)."""
+    def lag(s):
+        return np.array([(1 - s) * (1 - 2 * s), 4 * s * (1 - s), s * (2 * s - 1)])
+    return float(lag(t[1]) @ rho_cell @ lag(t[0]))
+
+
+def test_mh_never_moves_to_zero_density():
+    """Cells whose density is zero everywhere keep their chain at the cell centre; elsewhere no
+    particle sits where the interpolated density vanishes."""
+    mesh = I.UniformMesh(2, (4, 1))
+    om = O.OracleMesh.uniform(mesh)
+    nodes = I.uniform_q2_nodes(mesh)
+    rho = np.where(nodes[0] >= 0.5, 1.0 + nodes[1], 0.0)
+    counts = np.full(mesh.n_cells, 50, np.int32)
+    st, longest = O.seed_mh(om, counts, rho, 4, 5, 0, 1)
+    cs = st.cell_start
+    assert np.all(st.xr[:, cs[0]:cs[1]] == 0.5)   # every nodal value of cell 0 is zero
+    assert longest == 4 * 50
+    nx = 2 * mesh.n[0] + 1
+    R = rho.reshape(3, nx)
+    for K in (1, 2, 3):                           # cell 1 is zero except near its right face
+        for i in range(cs[K], cs[K + 1]):
+            assert _q2_numpy_scalar(R[:, 2 * K:2 * K + 3], st.xr[:, i]) > 0
+    # negative values count as zero density: with every state kept (J = 1) the chain stays at its start
+    # (the centre, where rho_h < 0) until a proposal with rho_h > 0 comes, and never visits other points
+    # of negative density
+    mesh = I.UniformMesh(2, (1, 1))
+    om = O.OracleMesh.uniform(mesh)
+    nodes = I.uniform_q2_nodes(mesh)
+    st, _ = O.seed_mh(om, np.array([80], np.int32), nodes[0] - 0.9, 1, 6, 0, 0)
+    xs = st.xr[:, : st.n]
+    at_start = np.all(xs == 0.5, axis=0)
+    assert at_start[0] and np.all(at_start | (xs[0] > 0.9)) and not np.all(at_start)
+
+
+def test_mh_samples_follow_the_density():
+    """One cell, density 1 + 2x (exact in Q2): the mean reference coordinate of 20,000 thinned samples
+    is 7/12 in x and 1/2 in y (standard error ~0.002; bound 0.01).  A reversed acceptance rule would
+    move the x mean below 1/2."""
+    mesh = I.UniformMesh(2, (1, 1))
+    om = O.OracleMesh.uniform(mesh)
+    nodes = I.uniform_q2_nodes(mesh)
+    st, longest = O.seed_mh(om, np.array([20000], np.int32), 1 + 2 * nodes[0], 10, 11, 0, 0)
+    m = st.xr[:, : st.n].mean(axis=1)
+    assert abs(m[0] - 7 / 12) < 0.01 and abs(m[1] - 0.5) < 0.01, m
+    assert longest < 60
+
+
+def test_mh_uniform_physical_density_on_a_distorted_cell():
+    """rho = 1 on a distorted quadrilateral: the samples are uniform in physical space, so their mean
+    is the cell's centroid (Gauss quadrature of the bilinear map), not the mean of its vertices (what
+    samples uniform in the reference cell would give): checks the |det grad Phi| factor."""
+    mesh = I.UniformMesh(2, (2, 2))
+    vert = I.uniform_vertices(mesh)
+    vert[:, 4] += [0.3, 0.25]                       # the interior vertex
+    om = O.OracleMesh.displaced(mesh, vert)
+    nn = int(np.prod(mesh.node_shape))
+    counts = np.array([20000, 0, 0, 0], np.int32)
+    st, _ = O.seed_mh(om, counts, np.ones(nn), 10, 12, 0, 0)
+    X = np.array([vert[:, 0], vert[:, 1], vert[:, 3], vert[:, 4]])     # v = va + 2 vb of cell 0
+    g, wg = np.polynomial.legendre.leggauss(8)
+    g, wg = 0.5 * (g + 1), 0.5 * wg
+    num, den = np.zeros(2), 0.0
+    for s, ws in zip(g, wg):
+        for t, wt in zip(g, wg):
+            N = np.array([(1 - s) * (1 - t), s * (1 - t), (1 - s) * t, s * t])
+            dNs = np.array([-(1 - t), 1 - t, -t, t])
+            dNt = np.array([-(1 - s), -s, 1 - s, s])
+            Jm = np.stack([X.T @ dNs, X.T @ dNt], axis=1)
+            det = abs(np.linalg.det(Jm))
+            num += ws * wt * det * (X.T @ N)
+            den += ws * wt * det
+    centroid = num / den
+    m = st.x[:, : st.n].mean(axis=1)
+    assert np.abs(m - centroid).max() < 0.006, (m, centroid)
+    assert np.abs(X.mean(axis=0) - centroid).max() > 0.02
