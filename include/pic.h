@@ -62,7 +62,15 @@ typedef enum {
 
 typedef enum { PIC_EULER = 1, PIC_RK2 = 2, PIC_RK4 = 4 } pic_scheme;
 typedef enum { PIC_F64 = 0, PIC_F32 = 1 } pic_prec;
-typedef enum { PIC_INTERP_CELL_AVERAGE = 0, PIC_INTERP_LINEAR_LS = 1 } pic_interp;
+typedef enum {
+    PIC_INTERP_CELL_AVERAGE = 0,      /* pic_interpolate */
+    PIC_INTERP_LINEAR_LS = 1,
+    PIC_INTERP_GEOMETRIC_AVERAGE = 2,
+    PIC_INTERP_HARMONIC_AVERAGE = 3,
+    PIC_INTERP_NEAREST = 4,           /* pic_interpolate_points */
+    PIC_INTERP_INV_DISTANCE = 5,
+    PIC_INTERP_SHAPE_WEIGHTED = 6
+} pic_interp;
 typedef enum { PIC_PROP_GIVEN = 0, PIC_PROP_INITIAL_POSITION = 1 } pic_prop_init;
 
 /* Marker for a lost particle in key arrays. */
@@ -187,6 +195,22 @@ PIC_API pic_status pic_current_buffer(pic_ctx *ctx, int32_t *which);
  * property j to coordinate j mod dim of x.  Replaces the current contents. */
 PIC_API pic_status pic_seed_reference(pic_ctx *ctx, const int32_t *counts, const double *xr, const uint32_t *ids,
                               int64_t n, int32_t prop_init, const void *prop_in);
+/* Metropolis-Hastings generation (Sec. 2.2): counts[K] particles in cell K
+ * (device int32 [n_cells]) drawn from the density rho (device double
+ * [n_nodes], nodal values of its Q2 interpolant rho_h; hanging-node values of
+ * an octree are used as given).  Per cell a chain in the reference cell with
+ * a proposal uniform in it, starting at its centre, target max(0, rho_h)
+ * |det grad Phi_K|; state i proposes coordinates u(seed, 1, K, i, axis) and
+ * accepts when u(seed, 2, K, i, 0) times the current target is below the
+ * proposal's, u the SplitMix64 counter hash of the population step; every
+ * J-th state (J-1, 2J-1, ...) becomes a particle.  Stored cell by cell with
+ * ids first_id + position, properties = initial position.  *longest_run
+ * (host, may be NULL) = the longest run of equal consecutive states over all
+ * chains: thinned particles repeat a location unless J exceeds it.  Replaces
+ * the current contents; PIC_ECAPACITY if the counts exceed the capacity,
+ * PIC_ENONFINITE for a non-finite density. */
+PIC_API pic_status pic_seed_mh(pic_ctx *ctx, const int32_t *counts, const double *rho, int32_t J, uint64_t seed,
+                               uint32_t first_id, int64_t *longest_run);
 /* Prescribed locations (Sec. 2.2, prescribed particle locations): locate each
  * x (device [dim][n]) in the mesh, drop points outside the domain, and store
  * the rest sorted by (cell, input order).  Properties as above. */
@@ -242,6 +266,26 @@ PIC_API pic_status pic_population(pic_ctx *ctx, int32_t min_pc, int32_t max_pc, 
  * particles or sigma_min/sigma_max of the design matrix is below 1e-10.
  * count [n_cells] receives the particle counts.  Device pointers, double. */
 PIC_API pic_status pic_interpolate(pic_ctx *ctx, int32_t kind, double *out, double *aux, int32_t *count);
+/* PIC_INTERP_GEOMETRIC_AVERAGE / PIC_INTERP_HARMONIC_AVERAGE (Sec. 2.7 (ii)):
+ * out [n_cells][n_prop] = exp of the mean logarithm / n over the sum of
+ * reciprocals of each property over the cell's particles (0 if a value is 0;
+ * the geometric mean is NaN if a value is negative; NaN for empty cells). */
+
+/* Particle -> evaluation points (Sec. 2.7 (i), (iii), (iv)): the points qhat
+ * (host [dim][n_q], reference coordinates in [0,1]^dim, 1 <= n_q <= 64, the
+ * same in every cell, e.g. quadrature points) get values from the particles
+ * of their own cell only:
+ *   PIC_INTERP_NEAREST         property of the particle nearest in physical
+ *                              distance to Phi_K(qhat) (ties: first in store
+ *                              order);
+ *   PIC_INTERP_INV_DISTANCE    weights 1 / |Phi_K(qhat) - x_k|^2, particles at
+ *                              the point itself share the whole weight;
+ *   PIC_INTERP_SHAPE_WEIGHTED  weights sum_v N_v(qhat) N_v(xhat_k) over the
+ *                              cell's d-linear vertex shape functions.
+ * out (device [n_cells][n_q][n_prop] double; NaN for empty cells), count
+ * (device [n_cells], may be NULL).  Allocates nothing. */
+PIC_API pic_status pic_interpolate_points(pic_ctx *ctx, int32_t kind, const double *qhat, int32_t n_q, double *out,
+                                          int32_t *count);
 
 /* ---- adjoint (derivative of the multi-step map w.r.t. the field) -------- */
 /* Bytes of device workspace for pic_advance_checkpointed with these sizes. */

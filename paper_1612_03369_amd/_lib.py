@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ECAPACITY, PIC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 PIC_EULER, PIC_RK2, PIC_RK4 = 1, 2, 4
 PIC_F64, PIC_F32 = 0, 1
-PIC_INTERP_CELL_AVERAGE, PIC_INTERP_LINEAR_LS = 0, 1
+PIC_INTERP_CELL_AVERAGE, PIC_INTERP_LINEAR_LS, PIC_INTERP_GEOMETRIC_AVERAGE, PIC_INTERP_HARMONIC_AVERAGE = 0, 1, 2, 3
+PIC_INTERP_NEAREST, PIC_INTERP_INV_DISTANCE, PIC_INTERP_SHAPE_WEIGHTED = 4, 5, 6
 PIC_PROP_GIVEN, PIC_PROP_INITIAL_POSITION = 0, 1
 PIC_LOST = 0xFFFFFFFF
 
@@ -30,7 +31,7 @@ EXPORTS = [
     "pic_set_velocity", "pic_set_velocity_end", "pic_shift_velocity", "pic_set_field_time", "pic_field_time",
     "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
     "pic_seed_reference", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
-    "pic_interpolate",
+    "pic_interpolate", "pic_interpolate_points", "pic_seed_mh",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
     "pic_batch_create", "pic_batch_advance", "pic_batch_set_schedule", "pic_batch_tune", "pic_batch_destroy",
@@ -95,6 +96,8 @@ def load(path: str | None = None):
             "pic_advance": (S, [P, D, I32, I32, I32]),
             "pic_set_property_odes": (S, [P, I32, I32, C.c_double, C.c_double]),
             "pic_set_velocity_end": (S, [P, P, I32, C.c_double]),
+            "pic_interpolate_points": (S, [P, I32, P, I32, P, P]),
+            "pic_seed_mh": (S, [P, P, P, I32, C.c_uint64, C.c_uint32, P]),
             "pic_shift_velocity": (S, [P, P, I32, C.c_double]),
             "pic_set_field_time": (S, [P, C.c_double]),
             "pic_field_time": (S, [P, P]),

@@ -262,7 +262,7 @@ class Problem:
         dev = self.device
         npr = self.store.n_prop
         cnt = torch.zeros(self.n_cells, dtype=torch.int32, device=dev)
-        if kind == L.PIC_INTERP_CELL_AVERAGE:
+        if kind in (L.PIC_INTERP_CELL_AVERAGE, L.PIC_INTERP_GEOMETRIC_AVERAGE, L.PIC_INTERP_HARMONIC_AVERAGE):
             out = torch.zeros((self.n_cells, npr), dtype=torch.float64, device=dev)
             self._chk(self.lib.pic_interpolate(self.h, kind, _ptr(out), None, _ptr(cnt)))
             return out, None, cnt
@@ -270,6 +270,31 @@ class Problem:
         aux = torch.zeros((self.n_cells, self.dim), dtype=torch.float64, device=dev)
         self._chk(self.lib.pic_interpolate(self.h, kind, _ptr(out), _ptr(aux), _ptr(cnt)))
         return out, aux, cnt
+
+    def interpolate_points(self, kind, qhat):
+        """Properties at the evaluation points qhat [dim][n_q] (reference coordinates, the same in every
+        cell) from the particles of each cell: returns out [n_cells][n_q][n_prop] and counts."""
+        torch = _torch()
+        q = np.ascontiguousarray(qhat, np.float64)
+        if q.ndim != 2 or q.shape[0] != self.dim:
+            raise ValueError(f"qhat must have shape ({self.dim}, n_q)")
+        out = torch.empty((self.n_cells, q.shape[1], self.store.n_prop), dtype=torch.float64, device=self.device)
+        cnt = torch.zeros(self.n_cells, dtype=torch.int32, device=self.device)
+        self._chk(self.lib.pic_interpolate_points(self.h, int(kind), _np_ptr(q), q.shape[1], _ptr(out), _ptr(cnt)))
+        return out, cnt
+
+    def seed_mh(self, counts, rho, J, seed, first_id=0):
+        """Metropolis-Hastings generation of counts[K] particles per cell from the nodal density rho
+        (Sec. 2.2); returns the longest run of equal consecutive chain states."""
+        torch = _torch()
+        c = torch.as_tensor(np.ascontiguousarray(counts, np.int32)).to(self.device)
+        r = torch.as_tensor(np.ascontiguousarray(rho, np.float64)).to(self.device).contiguous()
+        if r.shape != (self.n_nodes,):
+            raise ValueError(f"rho must have shape ({self.n_nodes},)")
+        longest = C.c_int64()
+        self._chk(self.lib.pic_seed_mh(self.h, _ptr(c), _ptr(r), int(J), int(seed), int(first_id),
+                                       C.byref(longest)))
+        return longest.value
 
     # ------------------------------------------------------------- adjoint
     def adjoint_workspace(self, n_steps, ckpt_every):

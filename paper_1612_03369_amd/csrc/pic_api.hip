@@ -1004,8 +1004,9 @@ extern "C" pic_status pic_interpolate(pic_ctx *c, int32_t kind, double *out, dou
     if (!out || !count) return fail(c, PIC_EINVAL, "null output");
     hipSetDevice(c->device);
     unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
-    if (kind == PIC_INTERP_CELL_AVERAGE) {
-        LAUNCH(c, "interp_average", k_interp_average, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, count);
+    if (kind == PIC_INTERP_CELL_AVERAGE || kind == PIC_INTERP_GEOMETRIC_AVERAGE || kind == PIC_INTERP_HARMONIC_AVERAGE) {
+        const int mode = kind == PIC_INTERP_CELL_AVERAGE ? 0 : (kind == PIC_INTERP_GEOMETRIC_AVERAGE ? 1 : 2);
+        LAUNCH(c, "interp_average", k_interp_average, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, count, mode);
     } else if (kind == PIC_INTERP_LINEAR_LS) {
         if (!aux) return fail(c, PIC_EINVAL, "linear least squares needs aux (xbar)");
         if (c->mesh.dim == 2) LAUNCH(c, "interp_lls", k_interp_lls<2>, grid, BLOCK, (const ProblemDev *)c->d_prob, 0, out, aux, count);
@@ -1014,6 +1015,130 @@ extern "C" pic_status pic_interpolate(pic_ctx *c, int32_t kind, double *out, dou
         return fail(c, PIC_EINVAL, "unknown interpolation kind %d", kind);
     }
     return PIC_OK;
+}
+
+namespace {
+template <int D>
+pic_status interp_points_launch(pic_ctx *c, int kind, const EvalPoints &qp, double *out, int32_t *count)
+{
+    unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
+    const ProblemDev *dp = c->d_prob;
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM: LAUNCH(c, "interp_points", (k_interp_points<D, MESH_UNIFORM>), grid, BLOCK, dp, 0, kind, qp, out, count); break;
+    case MESH_DISPLACED: LAUNCH(c, "interp_points", (k_interp_points<D, MESH_DISPLACED>), grid, BLOCK, dp, 0, kind, qp, out, count); break;
+    default:
+        if constexpr (D == 3) LAUNCH(c, "interp_points", (k_interp_points<3, MESH_OCTREE>), grid, BLOCK, dp, 0, kind, qp, out, count);
+    }
+    return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_interpolate_points(pic_ctx *c, int32_t kind, const double *qhat, int32_t n_q, double *out,
+                                             int32_t *count)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (kind != PIC_INTERP_NEAREST && kind != PIC_INTERP_INV_DISTANCE && kind != PIC_INTERP_SHAPE_WEIGHTED)
+        return fail(c, PIC_EINVAL, "unknown point interpolation kind %d", kind);
+    if (n_q < 1 || n_q > MAX_EVAL_POINTS) return fail(c, PIC_EINVAL, "n_q must be in [1, %d]", MAX_EVAL_POINTS);
+    if (!qhat || !out) return fail(c, PIC_EINVAL, "null argument");
+    const int d = c->mesh.dim;
+    EvalPoints qp{};
+    qp.n = n_q;
+    for (int a = 0; a < d; ++a)
+        for (int q = 0; q < n_q; ++q) {
+            const double v = qhat[a * n_q + q];
+            if (!(v >= 0.0 && v <= 1.0)) return fail(c, PIC_EINVAL, "evaluation points must lie in the reference cell");
+            qp.q[a][q] = v;
+        }
+    hipSetDevice(c->device);
+    const int k = kind - PIC_INTERP_NEAREST;
+    return d == 2 ? interp_points_launch<2>(c, k, qp, out, count) : interp_points_launch<3>(c, k, qp, out, count);
+}
+
+// ===========================================================================
+// Metropolis-Hastings generation
+// ===========================================================================
+namespace {
+template <int D>
+pic_status seed_mh_launch(pic_ctx *c, const double *rho, int J, uint64_t seed, uint32_t first_id,
+                          unsigned long long *d_longest)
+{
+    using V = typename NodeVec<D, double>::type;
+    const int64_t nn = c->mesh.n_nodes;
+    V *R = nullptr;
+    int *flag = nullptr;
+    pic_status s;
+    if ((s = dalloc(c, &R, (size_t)nn))) return s;
+    if ((s = dalloc(c, &flag, 1))) {
+        hipFree(R);
+        return s;
+    }
+    auto done = [&](pic_status st) {
+        hipStreamSynchronize(c->stream);
+        hipFree(R);
+        hipFree(flag);
+        return st;
+    };
+    if (hipMemsetAsync(flag, 0, sizeof(int), c->stream) != hipSuccess) return done(fail(c, PIC_EDEVICE, "memset"));
+    hipLaunchKernelGGL(k_pack_density<D>, dim3((unsigned)((nn + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, c->stream, rho, nn, R, flag);
+    int hflag = 0;
+    if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return done(fail(c, PIC_EDEVICE, "density copy"));
+    if (hflag) return done(fail(c, PIC_ENONFINITE, "density has NaN or infinite values"));
+    const unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK - 1) / BLOCK);
+    ProblemDev *dp = c->d_prob;
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM: hipLaunchKernelGGL((k_seed_mh<D, MESH_UNIFORM>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
+    case MESH_DISPLACED: hipLaunchKernelGGL((k_seed_mh<D, MESH_DISPLACED>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
+    default:
+        if constexpr (D == 3) hipLaunchKernelGGL((k_seed_mh<3, MESH_OCTREE>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest);
+    }
+    if (hipGetLastError() != hipSuccess) return done(fail(c, PIC_EDEVICE, "seed_mh launch"));
+    return done(PIC_OK);
+}
+}  // namespace
+
+extern "C" pic_status pic_seed_mh(pic_ctx *c, const int32_t *counts, const double *rho, int32_t J, uint64_t seed,
+                                  uint32_t first_id, int64_t *longest_run)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (!counts || !rho) return fail(c, PIC_EINVAL, "null argument");
+    if (J < 1) return fail(c, PIC_EINVAL, "J must be at least 1");
+    hipSetDevice(c->device);
+    std::vector<int32_t> h(c->mesh.n_cells);
+    HIPCHK(c, hipMemcpyAsync(h.data(), counts, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> cs(h.size() + 1, 0);
+    int64_t run = 0;
+    for (size_t k = 0; k < h.size(); ++k) {
+        if (h[k] < 0) return fail(c, PIC_EINVAL, "negative count");
+        cs[k] = (int32_t)run;
+        run += h[k];
+    }
+    cs[h.size()] = (int32_t)run;
+    if (run > c->store.capacity) return fail(c, PIC_ECAPACITY, "%lld particles exceed capacity %lld", (long long)run, (long long)c->store.capacity);
+    if ((uint64_t)first_id + (uint64_t)run > 0xFFFFFFFFull) return fail(c, PIC_EINVAL, "ids would overflow 32 bits");
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(c, &cur))) return s;
+    HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur], cs.data(), sizeof(int32_t) * cs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8 * (1 + STAT_STRIPES), c->stream));
+    unsigned long long *d_longest = nullptr;
+    if ((s = dalloc(c, &d_longest, 1))) return s;
+    HIPCHK(c, hipMemsetAsync(d_longest, 0, sizeof(unsigned long long), c->stream));
+    s = c->mesh.dim == 2 ? seed_mh_launch<2>(c, rho, J, seed, first_id, d_longest) : seed_mh_launch<3>(c, rho, J, seed, first_id, d_longest);
+    if (!s) {
+        LAUNCH(c, "seed", k_reduce_next_id, 1u, (unsigned)STAT_STRIPES, (const ProblemDev *)c->d_prob);
+        unsigned long long hl = 0;
+        if (hipMemcpyAsync(&hl, d_longest, sizeof(hl), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            s = fail(c, PIC_EDEVICE, "copy of the longest run");
+        if (!s && longest_run) *longest_run = (int64_t)hl;
+    }
+    hipFree(d_longest);
+    return s;
 }
 
 // ===========================================================================

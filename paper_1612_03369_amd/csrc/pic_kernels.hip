@@ -435,8 +435,11 @@ __device__ __forceinline__ double load_prop(const ProblemDev &P, const StoreDev 
 }
 
 // One wavefront per cell: arithmetic mean of every property (NaN if empty).
+// mode 0: arithmetic mean; 1: geometric, exp of the mean logarithm; 2:
+// harmonic, n over the sum of reciprocals (Sec. 2.7 (ii)).
 __global__ __launch_bounds__(BLOCK) void k_interp_average(const ProblemDev *__restrict__ probs, int prob,
-                                                          double *__restrict__ out, int32_t *__restrict__ count)
+                                                          double *__restrict__ out, int32_t *__restrict__ count,
+                                                          int mode)
 {
     const ProblemDev &P = probs[prob];
     const StoreDev cur = P.store[P.cur];
@@ -447,9 +450,120 @@ __global__ __launch_bounds__(BLOCK) void k_interp_average(const ProblemDev *__re
     if (lane == 0) count[K] = (int32_t)(e - b);
     for (int j = 0; j < P.n_prop; ++j) {
         double s = 0.0;
-        for (int64_t i = b + lane; i < e; i += 64) s += load_prop(P, cur, j, i);
+        for (int64_t i = b + lane; i < e; i += 64) {
+            const double v = load_prop(P, cur, j, i);
+            s += mode == 0 ? v : (mode == 1 ? log(v) : 1.0 / v);
+        }
         s = wave_sum(s);
-        if (lane == 0) out[K * P.n_prop + j] = (e > b) ? s / (double)(e - b) : __builtin_nan("");
+        const double n = (double)(e - b);
+        if (lane == 0)
+            out[K * P.n_prop + j] = (e == b) ? __builtin_nan("") : (mode == 0 ? s / n : (mode == 1 ? exp(s / n) : n / s));
+    }
+}
+
+// Evaluation points in reference coordinates, the same for every cell,
+// passed by value (no device allocation).
+constexpr int MAX_EVAL_POINTS = 64;
+struct EvalPoints {
+    double q[3][MAX_EVAL_POINTS];
+    int n;
+};
+
+// Wavefront minimum of (d2, index), ties to the lower index.
+__device__ __forceinline__ void wave_argmin(double &d2, int64_t &idx)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double od = __shfl_xor(d2, o, 64);
+        const int64_t oi = __shfl_xor(idx, o, 64);
+        if (od < d2 || (od == d2 && oi < idx)) {
+            d2 = od;
+            idx = oi;
+        }
+    }
+}
+
+/*
+ * One wavefront per cell: properties at the evaluation points from the
+ * cell's particles (Sec. 2.7): kind 0 nearest particle in physical distance
+ * (ties to the first in store order); 1 weights 1/|x_q - x_k|^2 (particles
+ * at the point share the whole weight); 2 weights prod_a [(1 - q_a)(1 - xr_a)
+ * + q_a xr_a], the sum over the cell's vertices of N_v(q) N_v(xr).
+ * out [n_cells][n_q][n_prop], NaN for empty cells.
+ */
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_interp_points(const ProblemDev *__restrict__ probs, int prob, int kind,
+                                                         EvalPoints qp, double *__restrict__ out,
+                                                         int32_t *__restrict__ count)
+{
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev cur = P.store[P.cur];
+    const int64_t cap = P.cap;
+    const int64_t K = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (K >= m.n_cells) return;
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1];
+    const int np = P.n_prop;
+    if (count && lane == 0) count[K] = (int32_t)(e - b);
+    for (int q = 0; q < qp.n; ++q) {
+        double* o = out + (K * qp.n + q) * np;
+        if (e == b) {
+            for (int j = lane; j < np; j += 64) o[j] = __builtin_nan("");
+            continue;
+        }
+        double tq[3] = {qp.q[0][q], qp.q[1][q], D == 3 ? qp.q[2][q] : 0.0}, xq[3];
+        map_to_real<D, KIND>(m, K, tq, xq);
+        auto dist2 = [&](int64_t i) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double r = cur.x[a * cap + i] - xq[a];
+                d2 = fma(r, r, d2);
+            }
+            return d2;
+        };
+        if (kind == 0) {
+            double bd = __builtin_inf();
+            int64_t bi = INT64_MAX;
+            for (int64_t i = b + lane; i < e; i += 64) {
+                const double d2 = dist2(i);
+                if (d2 < bd) {
+                    bd = d2;
+                    bi = i;
+                }
+            }
+            wave_argmin(bd, bi);
+            for (int j = lane; j < np; j += 64) o[j] = load_prop(P, cur, j, bi);
+            continue;
+        }
+        int hits = 0;
+        if (kind == 1) {
+            for (int64_t i = b + lane; i < e; i += 64) hits += dist2(i) == 0.0;
+            hits = wave_sum(hits);
+        }
+        for (int j = 0; j < np; ++j) {
+            double sw = 0.0, swp = 0.0;
+            for (int64_t i = b + lane; i < e; i += 64) {
+                double w;
+                if (kind == 1) {
+                    const double d2 = dist2(i);
+                    w = hits ? (d2 == 0.0 ? 1.0 : 0.0) : 1.0 / d2;
+                } else {
+                    w = 1.0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const double t = cur.xr[a * cap + i];
+                        w *= (1.0 - tq[a]) * (1.0 - t) + tq[a] * t;
+                    }
+                }
+                sw += w;
+                swp = fma(w, load_prop(P, cur, j, i), swp);
+            }
+            sw = wave_sum(sw);
+            swp = wave_sum(swp);
+            if (lane == 0) o[j] = swp / sw;
+        }
     }
 }
 
@@ -581,6 +695,93 @@ __device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t step, uint64_
     h = splitmix64(h ^ slot);
     h = splitmix64(h ^ axis);
     return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Scalar density repacked into the field layout (value in the first component).
+template <int D>
+__global__ void k_pack_density(const double *__restrict__ rho, int64_t nn, typename NodeVec<D, double>::type *R,
+                               int *nonfinite)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nn) return;
+    const double v = rho[g];
+    if (!isfinite(v)) atomicOr(nonfinite, 1);
+    typename NodeVec<D, double>::type r{};
+    r.x = v;
+    R[g] = r;
+}
+
+/*
+ * Metropolis-Hastings generation (Sec. 2.2), one thread per cell K: a chain
+ * in the reference cell with a proposal uniform in it, starting at its
+ * centre; state i proposes coordinates hash_u01(seed, 1, K, i, axis) and moves
+ * there when hash_u01(seed, 2, K, i, 0) * rho^(current) < rho^(proposal),
+ * rho^ = max(0, rho_h) |det grad Phi_K|.  States J-1, 2J-1, ... are written
+ * to the cell's slots of the current buffer (cell_start already set), ids
+ * first_id + slot, properties = initial position.  The longest run of equal
+ * consecutive states goes to *longest.
+ */
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_seed_mh(ProblemDev *probs, int prob,
+                                                   const typename NodeVec<D, double>::type *__restrict__ R, int J,
+                                                   uint64_t seed, uint32_t first_id, unsigned long long *longest)
+{
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev cur = P.store[P.cur];
+    const int64_t cap = P.cap;
+    const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= m.n_cells) return;
+    auto density = [&](const double *t) {
+        double u[3], Jm[3][3];
+        eval_q2<D, double, KIND>(m, R, K, t, u);
+        map_jacobian<D, KIND>(m, K, t, Jm);
+        const double det = D == 2 ? Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]
+                                  : Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
+                                        Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
+                                        Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+        return fmax(u[0], 0.0) * fabs(det);
+    };
+    const int64_t b = cur.cs[K], e = cur.cs[K + 1];
+    double t[3] = {0.5, 0.5, 0.5};
+    double rc = density(t);
+    long long run = 0, best = 0;
+    unsigned long long idmax = 0;
+    const long long n_states = (long long)J * (e - b);
+    int64_t p = b;
+    for (long long i = 0; i < n_states; ++i) {
+        double tp[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < D; ++a) tp[a] = hash_u01(seed, 1, (uint64_t)K, (uint64_t)i, (uint64_t)a);
+        const double rp = density(tp);
+        const double u = hash_u01(seed, 2, (uint64_t)K, (uint64_t)i, 0);
+        if (u * rc < rp) {
+            for (int a = 0; a < D; ++a) t[a] = tp[a];
+            rc = rp;
+            run = 1;
+        } else {
+            ++run;
+        }
+        best = run > best ? run : best;
+        if ((i + 1) % J == 0) {
+            double x[3];
+            map_to_real<D, KIND>(m, K, t, x);
+            for (int a = 0; a < D; ++a) {
+                cur.x[a * cap + p] = x[a];
+                cur.xr[a * cap + p] = t[a];
+            }
+            cur.cell[p] = (int32_t)K;
+            const uint32_t id = first_id + (uint32_t)p;
+            cur.id[p] = id;
+            for (int j = 0; j < P.n_prop; ++j) {
+                if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = x[j % D];
+                else ((float *)cur.prop)[j * cap + p] = (float)x[j % D];
+            }
+            idmax = idmax > (unsigned long long)id + 1ull ? idmax : (unsigned long long)id + 1ull;
+            ++p;
+        }
+    }
+    if (best) atomicMax(longest, (unsigned long long)best);
+    if (idmax) atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], idmax);
 }
 
 /*
