@@ -253,6 +253,10 @@ def run_main(args):
             extras["octree"] = bench_octree(args)
         if "odes" in args.extras:
             extras["odes"] = bench_odes(args)
+        if "time_field" in args.extras:
+            extras["time_field"] = bench_time_field(args)
+        if "interp" in args.extras:
+            extras["interp"] = bench_interp(args)
         line["extras"] = extras
 
     if not args.no_cpu_baseline:
@@ -482,6 +486,111 @@ def bench_odes(args):
     return r
 
 
+def bench_time_field(args):
+    """The 64^3 RK4 workload in a field that changes in time: u^n and u^{n+1} evaluated at every stage,
+    four particle steps per field step, the next field loaded (shift) after each field step."""
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Problem
+
+    cfg = I.config2(eval_f32=True)
+    mesh = cfg["mesh"]
+    n0 = cfg["xr"].shape[1]
+    nodes = I.uniform_q2_nodes(mesh)
+    fields = [torch.as_tensor(I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=2 + k).velocity, nodes))).cuda()
+              for k in range(3)]
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(fields[0])
+    p.allocate(n0, n_prop=3, prop_dtype="float32")
+    dt, sub = cfg["dt"], 4
+    n_field = max(1, args.steps // sub)
+
+    def run(timed_shift):
+        p.set_velocity(fields[0])
+        p.set_velocity_end(fields[1], sub * dt)
+        p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+        p.stats_reset()
+        torch.cuda.synchronize()
+        t_adv = t_shift = 0.0
+        for k in range(n_field):
+            t = time.perf_counter()
+            p.advance(dt, sub, L.PIC_RK4, L.PIC_F32)
+            torch.cuda.synchronize()
+            t_adv += time.perf_counter() - t
+            t = time.perf_counter()
+            p.shift_velocity(fields[(k + 2) % 3], sub * dt)
+            torch.cuda.synchronize()
+            t_shift += time.perf_counter() - t
+        return t_adv, t_shift
+
+    run(False)
+    t_adv, t_shift = run(True)
+    st = p.stats()
+    steps = n_field * sub
+    r = {"workload": cfg["name"] + "+time-interpolated", "particles": n0, "steps": steps, "substeps": sub,
+         "ms_per_step": 1e3 * t_adv / steps, "shift_ms": 1e3 * t_shift / n_field,
+         "particle_steps_per_s": st["particle_steps"] / t_adv}
+    log(f"[bench] time field: {r['ms_per_step']:.3f} ms/step, {r['particle_steps_per_s']:.3e} p-s/s, "
+        f"shift {r['shift_ms']:.2f} ms per field step")
+    p.close()
+    return r
+
+
+def bench_interp(args):
+    """On the 64^3 store (5,242,880 particles, three f64 properties): every interpolator, with the
+    eight Gauss points of Q1 plus the centre as evaluation points; and Metropolis-Hastings generation
+    of the same 20 particles per cell (J = 10) from a varying density."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1612_03369_amd import _lib as L
+    from paper_1612_03369_amd import inputs as I
+    from paper_1612_03369_amd.api import Problem
+
+    cfg = I.config2()
+    mesh = cfg["mesh"]
+    n0 = cfg["xr"].shape[1]
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n0, n_prop=3, prop_dtype="float64")
+    P = torch.rand((3, n0), dtype=torch.float64, device=p.device) + 0.5
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"], prop=P)
+    g = 1 / math.sqrt(3)
+    pts = np.array(list(np.ndindex(2, 2, 2)), float).T
+    q = np.concatenate([0.5 + (pts - 0.5) * g, np.full((3, 1), 0.5)], axis=1)
+    r = {"workload": cfg["name"] + " store", "particles": n0, "eval_points": q.shape[1]}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / reps
+
+    for name, kind in (("arithmetic", L.PIC_INTERP_CELL_AVERAGE), ("geometric", L.PIC_INTERP_GEOMETRIC_AVERAGE),
+                       ("harmonic", L.PIC_INTERP_HARMONIC_AVERAGE), ("linear_ls", L.PIC_INTERP_LINEAR_LS)):
+        r[name + "_ms"] = timed(lambda: p.interpolate(kind))
+    for name, kind in (("nearest", L.PIC_INTERP_NEAREST), ("inv_distance", L.PIC_INTERP_INV_DISTANCE),
+                       ("shape_weighted", L.PIC_INTERP_SHAPE_WEIGHTED)):
+        r[name + "_ms"] = timed(lambda: p.interpolate_points(kind, q))
+    nodes = I.uniform_q2_nodes(mesh)
+    rho = 1.0 + 0.5 * np.sin(6.0 * nodes[0]) * np.cos(4.0 * nodes[1]) + 0.3 * nodes[2]
+    lr = []
+    r["mh_seed_ms"] = timed(lambda: lr.append(p.seed_mh(cfg["counts"], rho, 10, 7)), reps=3)
+    r["mh_longest_run"] = lr[-1]
+    log(f"[bench] interpolators: " + ", ".join(f"{k[:-3]} {v:.2f} ms" for k, v in r.items() if k.endswith("_ms")))
+    p.close()
+    return r
+
+
 def cpu_baseline(args):
     """FP64 oracle on the host cores: the first steps of the same workload."""
     from oracle import oracle as O
@@ -512,7 +621,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--extras", default="adjoint,batch,octree,odes", help="comma list: adjoint,batch,octree,odes ('' for none)")
+    ap.add_argument("--extras", default="adjoint,batch,octree,odes,time_field,interp",
+                    help="comma list: adjoint,batch,octree,odes,time_field,interp ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
