@@ -86,6 +86,8 @@ def lib():
             L.orc_interp_points.restype = None
             L.orc_seed_mh.argtypes = [P, P, P, C.c_int, C.c_uint64, C.c_uint32, P, P]
             L.orc_seed_mh.restype = C.c_int
+            L.orc_transfer.argtypes = [P, P, P, P]
+            L.orc_transfer.restype = C.c_int
             L.orc_sort_perm.argtypes = [C.c_int64, C.c_int64, P, P, P, P]
             L.orc_step.restype = C.c_int
             L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, P, P, P]
@@ -385,6 +387,17 @@ def advect_odes(mesh: OracleMesh, U, dt, scheme, st: OracleStore, alpha, beta, d
                                 int(scheme), float(alpha), float(beta), int(damage_prop), int(deform_prop),
                                 C.byref(st.c), _p(key), _p(near))
     return key[: st.n], near[: st.n]
+
+
+def transfer(new_mesh: OracleMesh, src: OracleStore, cap=None):
+    """Particles of src moved to the refined/coarsened mesh new_mesh (Sec. 2.5): located there, reference
+    location recomputed, stable sort by new cell; returns the new store."""
+    dst = OracleStore(new_mesh.dim, cap or max(src.n, 1), src.n_prop)
+    cs = np.zeros(new_mesh.n_cells + 1, np.int64)
+    if lib().orc_transfer(C.byref(new_mesh.c), C.byref(src.c), C.byref(dst.c), _p(cs)) != 0:
+        raise ValueError("capacity too small")
+    dst.cell_start = cs
+    return dst
 
 
 def stable_sort_perm(n_cells, old_cell, key):

@@ -858,6 +858,53 @@ int orc_step(const orc_mesh *m, const double *U, int64_t nn, double dt, int sche
     return 0;
 }
 
+/*
+ * Particles after mesh refinement or coarsening (Sec. 2.5): every particle of
+ * store `src` (on the old mesh) goes to the cell of the new mesh m that holds
+ * its location -- a child of its old cell when that was refined, the parent
+ * when it was coarsened -- with its reference location recomputed there;
+ * location, id and properties are kept, particles outside m are dropped.
+ * The result is stored in dst sorted by new cell, in the old store order
+ * within a cell (a stable sort).  dst->n_prop must equal src->n_prop; returns
+ * -1 if dst is too small.  cell_start [n_cells(m)+1] receives the new offsets.
+ */
+int orc_transfer(const orc_mesh *m, const orc_store *src, orc_store *dst, int64_t *cell_start)
+{
+    int d = m->dim;
+    int64_t n = src->n, nc = orc_n_cells(m);
+    if (n > dst->cap) return -1;
+    int32_t *key = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double *xr = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double x[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) x[a] = src->x[a * src->cap + i];
+        if (!orc_locate(m, x, &key[i], xr + 3 * i)) key[i] = -1;
+    }
+    /* counting sort by new cell, stable */
+    for (int64_t K = 0; K <= nc; ++K) cell_start[K] = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (key[i] >= 0) cell_start[key[i] + 1]++;
+    for (int64_t K = 0; K < nc; ++K) cell_start[K + 1] += cell_start[K];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc > 0 ? nc : 1));
+    for (int64_t K = 0; K < nc; ++K) fill[K] = cell_start[K];
+    for (int64_t i = 0; i < n; ++i) {
+        if (key[i] < 0) continue;
+        int64_t p = fill[key[i]]++;
+        for (int a = 0; a < d; ++a) {
+            dst->x[a * dst->cap + p] = src->x[a * src->cap + i];
+            dst->xr[a * dst->cap + p] = xr[3 * i + a];
+        }
+        dst->cell[p] = key[i];
+        dst->id[p] = src->id[i];
+        for (int j = 0; j < src->n_prop; ++j) dst->prop[j * dst->cap + p] = src->prop[j * src->cap + i];
+    }
+    dst->n = cell_start[nc];
+    free(key);
+    free(xr);
+    free(fill);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* counter-based random numbers: SplitMix64 (Steele, Lea, Flood 2014)   */
 /* ------------------------------------------------------------------ */

@@ -316,6 +316,59 @@ def balance_octree(level, anchor, max_level):
     return np.array(lv, np.uint8)[order], np.ascontiguousarray(A[:, order].astype(np.int32))
 
 
+def morton_sort(level, anchor, max_level):
+    """Leaves listed in Morton order of their anchors (finest-cell units)."""
+    A = np.asarray(anchor, np.int64)
+    key = np.zeros(A.shape[1], dtype=np.uint64)
+    for bit in range(max_level):
+        for ax in range(3):
+            key |= ((A[ax].astype(np.uint64) >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + ax)
+    order = np.argsort(key, kind="stable")
+    return np.asarray(level, np.uint8)[order], np.ascontiguousarray(A[:, order].astype(np.int32))
+
+
+def refine_leaves(level, anchor, max_level, mask):
+    """Replace every leaf with mask set (and level < max_level) by its eight children."""
+    level = np.asarray(level)
+    anchor = np.asarray(anchor, np.int64)
+    mask = np.asarray(mask, bool) & (level < max_level)
+    keep_l, keep_a = level[~mask], anchor[:, ~mask]
+    pl, pa = level[mask].astype(np.int64), anchor[:, mask]
+    kids_l, kids_a = [], []
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                h = (1 << (max_level - pl - 1))
+                kids_a.append(pa + np.stack([dx * h, dy * h, dz * h]))
+                kids_l.append(pl + 1)
+    L = np.concatenate([keep_l.astype(np.int64)] + kids_l)
+    A = np.concatenate([keep_a] + kids_a, axis=1)
+    return morton_sort(L, A, max_level)
+
+
+def coarsen_leaves(level, anchor, max_level, mask):
+    """Merge every complete group of eight sibling leaves that all have mask set into their parent."""
+    level = np.asarray(level).astype(np.int64)
+    anchor = np.asarray(anchor, np.int64)
+    mask = np.asarray(mask, bool) & (level > 0)
+    groups = {}
+    for k in np.nonzero(mask)[0]:
+        ps = 1 << (max_level - level[k] + 1)                 # parent size in finest units
+        pa = tuple(int(v) for v in (anchor[:, k] // ps) * ps)
+        groups.setdefault((int(level[k]), pa), []).append(k)
+    merged = set()
+    new_l, new_a = [], []
+    for (lv, pa), ks in groups.items():
+        if len(ks) == 8:
+            merged.update(ks)
+            new_l.append(lv - 1)
+            new_a.append(pa)
+    keep = np.array([k for k in range(level.size) if k not in merged], np.int64)
+    L = np.concatenate([level[keep], np.array(new_l, np.int64)])
+    A = np.concatenate([anchor[:, keep], np.array(new_a, np.int64).T.reshape(3, -1)], axis=1)
+    return morton_sort(L, A, max_level)
+
+
 # --------------------------------------------------------------------------
 # workload configurations
 # --------------------------------------------------------------------------

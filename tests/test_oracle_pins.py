@@ -1030,3 +1030,87 @@ def test_mh_uniform_physical_density_on_a_distorted_cell():
     m = st.x[:, : st.n].mean(axis=1)
     assert np.abs(m - centroid).max() < 0.006, (m, centroid)
     assert np.abs(X.mean(axis=0) - centroid).max() > 0.02
+
+
+# ----------------------------------------------------------------------------
+# particles after mesh refinement and coarsening (Sec. 2.5)
+# ----------------------------------------------------------------------------
+def _octree_store(seed):
+    level, anchor = I.octree_shell_leaves(base_level=1, max_level=4, r_in=0.0, r_out=0.3, width=1.0,
+                                          centre=(0.3, 0.35, 0.4))
+    level, anchor = I.balance_octree(level, anchor, 4)
+    om = O.OracleMesh.octree(level, anchor, 4)
+    counts = np.random.default_rng(seed).integers(0, 9, level.size).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=seed + 1)
+    st = O.seed(om, counts, xr, ids, 2)
+    return level, anchor, om, st
+
+
+def test_transfer_to_refined_cells_closed_form():
+    """Refining a leaf splits it at its midpoints: a particle at xhat goes to child b = floor(2 xhat) with
+    reference location 2 xhat - b; other leaves keep their particles unchanged; within a new cell the
+    old store order is kept; nothing is lost."""
+    level, anchor, om, st = _octree_store(4000)
+    mask = (np.arange(level.size) % 3 == 0) & (level < 4)
+    nl, na = I.refine_leaves(level, anchor, 4, mask)
+    nm = O.OracleMesh.octree(nl, na, 4)
+    dst = O.transfer(nm, st)
+    assert dst.n == st.n
+    old_pos = {int(i): k for k, i in enumerate(st.id[: st.n])}
+    s = 1 << 4
+    n_checked = 0
+    for p in range(dst.n):
+        k = old_pos[int(dst.id[p])]
+        Ko, Kn = int(st.cell[k]), int(dst.cell[p])
+        t = st.xr[:, k]
+        assert np.array_equal(dst.x[:, p], st.x[:, k]) and np.array_equal(dst.prop[:, p], st.prop[:, k])
+        if not mask[Ko]:
+            assert nl[Kn] == level[Ko] and np.array_equal(na[:, Kn], anchor[:, Ko])
+            assert np.abs(dst.xr[:, p] - t).max() <= 1e-15
+            continue
+        if np.min(np.abs(t - 0.5)) < 1e-12:
+            continue
+        b = (t >= 0.5).astype(int)
+        h = s >> (int(level[Ko]) + 1)
+        assert nl[Kn] == level[Ko] + 1 and np.array_equal(na[:, Kn], anchor[:, Ko] + b * h)
+        assert np.abs(dst.xr[:, p] - (2 * t - b)).max() <= 4e-15
+        n_checked += 1
+    assert n_checked > 100
+    # stable: within each new cell the particles keep their old relative order
+    cs = dst.cell_start
+    for K in range(nm.n_cells):
+        ks = [old_pos[int(i)] for i in dst.id[cs[K]:cs[K + 1]]]
+        assert ks == sorted(ks)
+
+
+def test_transfer_to_coarsened_cells_and_back():
+    """Coarsening merges eight siblings: the parent's reference location is (xhat + b) / 2 for the
+    particle of child b; refining again gives every particle its original cell and reference location
+    (up to rounding) and every cell its original set of particles."""
+    level, anchor, om, st = _octree_store(4010)
+    cl, ca = I.coarsen_leaves(level, anchor, 4, level == 4)
+    assert cl.size < level.size
+    cm = O.OracleMesh.octree(cl, ca, 4)
+    mid = O.transfer(cm, st)
+    assert mid.n == st.n
+    old_pos = {int(i): k for k, i in enumerate(st.id[: st.n])}
+    merged = 0
+    for p in range(mid.n):
+        k = old_pos[int(mid.id[p])]
+        Ko, Kn = int(st.cell[k]), int(mid.cell[p])
+        if cl[Kn] == level[Ko] - 1:
+            h = (1 << 4) >> int(level[Ko])
+            b = (anchor[:, Ko] - ca[:, Kn]) // h
+            assert np.abs(mid.xr[:, p] - (st.xr[:, k] + b) / 2).max() <= 1e-15
+            merged += 1
+    assert merged > 100
+    back = O.transfer(om, mid)
+    cs0, cs1 = st.cell_start, back.cell_start
+    assert np.array_equal(cs0, cs1)
+    for K in range(om.n_cells):
+        a = st.id[cs0[K]:cs0[K + 1]]
+        b = back.id[cs1[K]:cs1[K + 1]]
+        assert np.array_equal(np.sort(a), np.sort(b))
+    pos = {int(i): k for k, i in enumerate(back.id[: back.n])}
+    idx = np.array([pos[int(i)] for i in st.id[: st.n]])
+    assert np.abs(back.xr[:, idx] - st.xr[:, : st.n]).max() <= 4e-15
