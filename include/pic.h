@@ -223,6 +223,22 @@ PIC_API pic_status pic_seed_positions(pic_ctx *ctx, const double *x, const uint3
  * LDS). */
 PIC_API pic_status pic_set_tile(pic_ctx *ctx, int32_t tile_cells);
 
+/* ---- mesh refinement and coarsening (Sec. 2.5) ------------------------- */
+/* Move the particles of `from` (its current buffer, on the mesh before
+ * refinement or coarsening) into `to` (a problem on the new mesh over the same
+ * box, with a bound store): every particle goes to the cell of the new mesh
+ * holding its location -- a child of its cell when that was refined, the
+ * parent when it was coarsened -- with its reference location recomputed
+ * there; location, id and properties are kept; particles outside the new
+ * mesh are dropped (counted as lost).  `to` ends sorted by new cell with the
+ * old store order kept within a cell, its next id no smaller than the
+ * source's.  More particles on refinement / fewer on coarsening: call
+ * pic_population on `to` afterwards.  `from` is not changed.  Needs one
+ * device, one dimension, the same property count and precision
+ * (PIC_EINVAL) and room for the particles (PIC_ECAPACITY).  Synchronises
+ * both streams. */
+PIC_API pic_status pic_transfer(pic_ctx *from, pic_ctx *to);
+
 /* ---- properties integrated along the trajectories (Sec. 2.6) ----------- */
 /* Switch on the two property equations of Sec. 2.6 for pic_advance:
  *   damage       d' = alpha |eps(u)| - beta d, eps = (grad u + grad u^T)/2,

@@ -283,6 +283,11 @@ class Problem:
         self._chk(self.lib.pic_interpolate_points(self.h, int(kind), _np_ptr(q), q.shape[1], _ptr(out), _ptr(cnt)))
         return out, cnt
 
+    def transfer_from(self, other: "Problem"):
+        """Take the particles of `other` (the mesh before refinement or coarsening, Sec. 2.5): located in
+        this mesh, reference locations recomputed, stable by new cell.  `other` is unchanged."""
+        self._chk(self.lib.pic_transfer(other.h, self.h))
+
     def seed_mh(self, counts, rho, J, seed, first_id=0):
         """Metropolis-Hastings generation of counts[K] particles per cell from the nodal density rho
         (Sec. 2.2); returns the longest run of equal consecutive chain states."""

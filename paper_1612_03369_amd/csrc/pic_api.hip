@@ -906,6 +906,58 @@ extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint
     return PIC_OK;
 }
 
+namespace {
+template <int D>
+pic_status transfer_launch(pic_ctx *c, const ProblemDev *src, int64_t n)
+{
+    const unsigned grid = (unsigned)std::max<int64_t>(1, (n + BLOCK - 1) / BLOCK);
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM: LAUNCH(c, "transfer", (k_transfer_in<D, MESH_UNIFORM>), grid, BLOCK, src, c->d_prob, 0, n); break;
+    case MESH_DISPLACED: LAUNCH(c, "transfer", (k_transfer_in<D, MESH_DISPLACED>), grid, BLOCK, src, c->d_prob, 0, n); break;
+    default:
+        if constexpr (D == 3) LAUNCH(c, "transfer", (k_transfer_in<3, MESH_OCTREE>), grid, BLOCK, src, c->d_prob, 0, n);
+    }
+    return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_transfer(pic_ctx *from, pic_ctx *to)
+{
+    if (!from || !to || from == to) return PIC_EINVAL;
+    pic_status s = require_ready(to, false);
+    if (s) return s;
+    if ((s = require_ready(from, false))) return fail(to, s, "source: %s", from->err.c_str());
+    if (from->device != to->device) return fail(to, PIC_EINVAL, "both problems must be on one device");
+    if (from->mesh.dim != to->mesh.dim) return fail(to, PIC_EINVAL, "dimensions differ");
+    if (from->store.n_prop != to->store.n_prop || (from->store.n_prop && from->store.prop_prec != to->store.prop_prec))
+        return fail(to, PIC_EINVAL, "property count or precision differs");
+    for (int a = 0; a < to->mesh.dim; ++a)
+        if (from->mesh.lo[a] != to->mesh.lo[a] || from->mesh.hi[a] != to->mesh.hi[a])
+            return fail(to, PIC_EINVAL, "the two meshes cover different boxes");
+    hipSetDevice(to->device);
+    // the source's pending work, then its live count
+    HIPCHK(to, hipStreamSynchronize(from->stream));
+    int32_t scur = 0, n32 = 0;
+    if ((s = pic_current_buffer(from, &scur))) return fail(to, s, "source: %s", from->err.c_str());
+    HIPCHK(to, hipMemcpy(&n32, from->store.cell_start[scur] + from->mesh.n_cells, sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int64_t n = n32;
+    if (n > to->store.capacity) return fail(to, PIC_ECAPACITY, "%lld particles exceed capacity %lld", (long long)n, (long long)to->store.capacity);
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(to, &cur))) return s;
+    const int64_t nc = to->mesh.n_cells;
+    HIPCHK(to, hipMemsetAsync(to->scr.n_stay, 0, sizeof(int32_t) * nc, to->stream));
+    HIPCHK(to, hipMemsetAsync(to->scr.n_arrive, 0, sizeof(int32_t) * nc, to->stream));
+    HIPCHK(to, hipMemsetAsync(to->scr.cursor, 0, sizeof(int32_t) * (nc + 1), to->stream));
+    HIPCHK(to, hipMemsetAsync(to->scr.next_id, 0, 8 * (1 + STAT_STRIPES), to->stream));
+    HIPCHK(to, hipMemcpyAsync(to->store.cell_start[cur] + nc, &n32, sizeof(int32_t), hipMemcpyHostToDevice, to->stream));
+    s = to->mesh.dim == 2 ? transfer_launch<2>(to, from->d_prob, n) : transfer_launch<3>(to, from->d_prob, n);
+    if (s) return s;
+    LAUNCH(to, "transfer", k_reduce_next_id, 1u, (unsigned)STAT_STRIPES, (const ProblemDev *)to->d_prob);
+    if ((s = enqueue_sort(to, to->d_prob, 0, true))) return s;
+    HIPCHK(to, hipStreamSynchronize(to->stream));
+    return PIC_OK;
+}
+
 // ===========================================================================
 // advance
 // ===========================================================================

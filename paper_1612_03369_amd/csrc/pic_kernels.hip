@@ -382,6 +382,55 @@ __global__ void k_reduce_next_id(const ProblemDev *probs)
 // Prescribed locations: locate each point with the global search and write it
 // to the current buffer unsorted; key = cell (or LOST), every point counted as
 // an arrival so that the sort machinery orders by (cell, input order).
+// Particles of another problem's current buffer (the mesh before refinement
+// or coarsening, Sec. 2.5) as an unsorted input of this problem: located in
+// this mesh (a child of the old cell after refinement, the parent after
+// coarsening), reference location recomputed; location, id and properties
+// copied.  The re-sort that follows orders them by (new cell, old order).
+template <int D, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_transfer_in(const ProblemDev *src_probs, ProblemDev *probs, int prob, int64_t n)
+{
+    const ProblemDev &S = src_probs[0];
+    const ProblemDev &P = probs[prob];
+    const MeshDev &m = P.mesh;
+    const StoreDev src = S.store[S.cur];
+    const StoreDev cur = P.store[P.cur];
+    const int64_t scap = S.cap, cap = P.cap;
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p == 0) atomicMax(&P.scr.next_id[1], S.scr.next_id[0]);
+    if (p >= n) return;
+    double x[3], t[3];
+    for (int a = 0; a < D; ++a) x[a] = src.x[a * scap + p];
+    int32_t K = -1;
+    LocStats ls = {0, 0, 0, 0};
+    bool ok = in_box_domain<D>(m, x);
+    if (ok) {
+        if constexpr (KIND == MESH_UNIFORM) {
+            ok = locate<D, KIND>(m, x, 0, K, t, ls);
+        } else if constexpr (KIND == MESH_OCTREE) {
+            K = octree_lookup(m, x);
+            map_to_ref<D, KIND>(m, K, x, t);
+        } else {
+            ok = global_search_displaced<D>(m, x, K, t, ls);
+        }
+    }
+    for (int a = 0; a < D; ++a) {
+        cur.x[a * cap + p] = x[a];
+        cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+    }
+    cur.cell[p] = -1;
+    const uint32_t id = src.id[p];
+    cur.id[p] = id;
+    for (int j = 0; j < P.n_prop; ++j) {
+        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = ((const double *)src.prop)[j * scap + p];
+        else ((float *)cur.prop)[j * cap + p] = ((const float *)src.prop)[j * scap + p];
+    }
+    P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
+    if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
+    else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
+    atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], (unsigned long long)id + 1ull);
+}
+
 template <int D, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int prob, const double *__restrict__ x_in,
                                                           const uint32_t *__restrict__ ids, int64_t n, int prop_init,
