@@ -369,6 +369,18 @@ def coarsen_leaves(level, anchor, max_level, mask):
     return morton_sort(L, A, max_level)
 
 
+def coarsen_finest(level, anchor, max_level):
+    """Merge every group of eight sibling leaves at the finest level into its parent (vectorised; in a
+    tree built by refinement the finest leaves always come in complete sibling groups)."""
+    level = np.asarray(level).astype(np.int64)
+    anchor = np.asarray(anchor, np.int64)
+    fine = level == max_level
+    parents = np.unique(((anchor[:, fine] >> 1) << 1).T, axis=0).T
+    L = np.concatenate([level[~fine], np.full(parents.shape[1], max_level - 1)])
+    A = np.concatenate([anchor[:, ~fine], parents], axis=1)
+    return morton_sort(L, A, max_level)
+
+
 # --------------------------------------------------------------------------
 # workload configurations
 # --------------------------------------------------------------------------
