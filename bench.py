@@ -429,6 +429,28 @@ def bench_octree(args):
          "cells_min_max": [int(c.min()), int(c.max())]}
     log(f"[bench] octree: {steps} steps: advect+sort {adv:.1f} ms ({r['particle_steps_per_s']:.3e} p-s/s), "
         f"population {pop:.1f} ms, LLS {lls:.2f} ms, live {st['live']}")
+    # mesh coarsening and refinement (Sec. 2.5): every finest sibling group merged, then split again
+    cl, ca = I.coarsen_finest(cfg["level"], cfg["anchor"], cfg["max_level"])
+    q = Problem(0)
+    q.mesh_octree(cl, ca, cfg["max_level"])
+    q.set_velocity(np.zeros((3, q.n_nodes)))
+    q.allocate(cap, n_prop=cfg["n_prop"], prop_dtype="float64")
+
+    def timed_transfer(dst, src):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst.transfer_from(src)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t)
+
+    timed_transfer(q, p)                             # warm-up
+    r["coarse_leaves"] = int(cl.size)
+    r["transfer_coarsen_ms"] = timed_transfer(q, p)
+    r["transfer_refine_ms"] = timed_transfer(p, q)
+    r["transferred"] = p.stats()["live"]
+    log(f"[bench] octree: transfer of {r['transferred']} particles to the coarsened mesh ({cl.size} leaves) "
+        f"{r['transfer_coarsen_ms']:.1f} ms, back to the fine mesh {r['transfer_refine_ms']:.1f} ms")
+    q.close()
     p.close()
     return r
 
