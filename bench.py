@@ -139,7 +139,7 @@ def bytes_per_particle(kernel, dim=3, prop_bytes=12):
     }[kernel]
 
 
-KERNELS = ("advect", "gather_advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip")
+KERNELS = ("advect", "gather_advect", "scan_reduce", "scan_down", "place", "fix", "gather", "flip")
 
 
 def run_main(args):

@@ -366,7 +366,6 @@ pic_status set_dt(pic_ctx *c, double dt)
 pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode)
 {
     LAUNCH(c, "scan_reduce", k_scan_reduce, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
-    LAUNCH(c, "scan_top", k_scan_top, 1u, BLOCK, (const ProblemDev *)dp, 1);
     LAUNCH(c, "scan_down", k_scan_down, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
     return PIC_OK;
 }
@@ -1255,9 +1254,10 @@ extern "C" pic_status pic_profile_read(pic_ctx *c, const char *kernel, double *t
     if (it == c->prof.end()) {
         if (total_ms) *total_ms = 0.0;
         if (launches) *launches = 0;
-        static const char *known[] = {"advect", "scan_reduce", "scan_top", "scan_down", "place", "fix", "gather", "flip",
+        static const char *known[] = {"advect", "scan_reduce", "scan_down", "place", "fix", "gather", "flip",
                                       "seed", "seed_positions", "population", "population_finish", "interp_average",
-                                      "interp_lls", "adjoint_step", "adjoint_save", "batch_advect", "gather_advect"};
+                                      "interp_lls", "interp_points", "transfer", "adjoint_step", "adjoint_save", "batch_advect",
+                                      "gather_advect"};
         for (const char *k : known)
             if (!std::strcmp(k, kernel)) return PIC_OK;
         return fail(c, PIC_EINVAL, "unknown kernel name %s", kernel);

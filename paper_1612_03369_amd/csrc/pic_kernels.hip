@@ -10,7 +10,7 @@
 namespace pic {
 
 // ===========================================================================
-// scan of the new per-cell counts (three phases over chunks of cells)
+// scan of the new per-cell counts (two phases over chunks of cells)
 // ===========================================================================
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
@@ -68,28 +68,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restr
     }
 }
 
-// One workgroup per problem: exclusive scan over that problem's chunk sums.
-__global__ __launch_bounds__(BLOCK) void k_scan_top(const ProblemDev *__restrict__ probs, int n_probs)
-{
-    __shared__ int64_t s_tmp[BLOCK / 64];
-    for (int p = blockIdx.x; p < n_probs; p += gridDim.x) {
-        const ProblemDev &P = probs[p];
-        const int nch = (int)((P.mesh.n_cells + SCAN_CHUNK - 1) / SCAN_CHUNK);
-        int64_t carry = 0;
-        for (int b = 0; b < nch; b += BLOCK) {
-            int c = b + threadIdx.x;
-            int64_t v = c < nch ? P.scr.chunk[c] : 0;
-            int64_t total;
-            int64_t pre = block_scan_i64(v, s_tmp, total);
-            if (c < nch) P.scr.chunk[c] = carry + pre;
-            carry += total;
-        }
-        if (threadIdx.x == 0) P.scr.chunk[nch] = carry;
-    }
-}
-
-// Local scan + chunk offset -> cell_start of the other buffer.  Mode 0 also
-// resets the arrival counters and the placement cursors for the next step.
+// Local scan + chunk offset -> cell_start of the other buffer.  The chunk's
+// offset is the sum of the preceding chunks' totals of its problem, added up
+// by the workgroup itself (a few hundred values at most).  Mode 0 also
+// resets the arrival counters and sets each cell's placement cursor to its
+// first arrival slot (after its stayers).
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
                                                      int n_items, int mode)
 {
@@ -107,8 +90,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
             v[k] = K < nc ? cell_value(P, K, mode) : 0;
             sum += v[k];
         }
-        int64_t total;
-        int64_t run = block_scan_i64(sum, s_tmp, total) + P.scr.chunk[it.chunk];
+        int64_t before = 0, offset, total;
+        for (int c = threadIdx.x; c < it.chunk; c += BLOCK) before += P.scr.chunk[c];
+        block_scan_i64(before, s_tmp, offset);
+        int64_t run = block_scan_i64(sum, s_tmp, total) + offset;
         const int64_t nch = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             int64_t K = K0 + k;
@@ -116,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
                 if (mode == 0) {
                     nxt.cs[K] = (int32_t)run;
                     P.scr.n_arrive[K] = 0;
-                    P.scr.cursor[K] = 0;
+                    P.scr.cursor[K] = (int32_t)run + P.scr.n_stay[K];
                 } else {
                     nxt.cs[K] = (int32_t)(run & 0xFFFFFFFFll);
                     P.scr.cursor[K] = (int32_t)(run >> 32);     // first new-id offset of the cell
@@ -125,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
             run += v[k];
         }
         if (it.chunk == nch - 1 && threadIdx.x == 0) {
-            int64_t tot = P.scr.chunk[nch];
+            const int64_t tot = offset + total;
             nxt.cs[nc] = (int32_t)(mode == 0 ? tot : (tot & 0xFFFFFFFFll));
             if (mode == 1) P.scr.cursor[nc] = (int32_t)(tot >> 32);
         }
@@ -140,7 +125,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
  * new_start[K] + (rank among the cell's stayers): a workgroup prefix scan of
  * stay flags in store order, minus the scan value at the cell's first
  * particle.  Arrivals get a provisional slot after the destination cell's
- * stayers from an atomic cursor; k_fix orders them afterwards.
+ * stayers from an atomic cursor (each cell's first arrival slot, set by the
+ * scan); k_fix orders them afterwards.
  */
 __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ probs, const WorkItem *__restrict__ work,
                                                  int n_work)
@@ -189,13 +175,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
             if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
             __syncthreads();
             if (active && key != LOST) {
-                int64_t dst;
-                if (stay) {
-                    dst = (int64_t)s_ncs[kloc] + (Pi - s_base[kloc]);
-                } else {
-                    const int64_t b = (int64_t)nxt.cs[key] + P.scr.n_stay[key];
-                    dst = b + atomicAdd(&P.scr.cursor[key], 1);
-                }
+                const int64_t dst = stay ? (int64_t)s_ncs[kloc] + (Pi - s_base[kloc]) : atomicAdd(&P.scr.cursor[key], 1);
                 P.scr.src[dst] = i;
             }
             carry += total;
@@ -219,8 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
         if (i >= n || i >= it.end) continue;
         const uint32_t key = P.scr.key[P.cur][i];
         if (key == LOST) continue;
-        const int r = atomicAdd(&P.scr.cursor[key], 1);
-        P.scr.src[(int64_t)nxt.cs[key] + P.scr.n_stay[key] + r] = (int32_t)i;
+        P.scr.src[atomicAdd(&P.scr.cursor[key], 1)] = (int32_t)i;
     }
 }
 
