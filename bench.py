@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 REPO = os.path.dirname(os.path.abspath(__file__))
 # byte counters of the dominant kernel, taken by --summarize-traffic from two rocprofv3 --pmc runs
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_gather_advect_uniform64_rk4_f32.json")
-DOMINANT_KERNEL = "k_advect_blk<3, 4, float, 4, 4, 4, true>"
+DOMINANT_KERNEL = "k_advect_blk<3, 4, float, 4, 4, 4, true, false, false>"
 COPY_BYTES = 64 * 1024 * 1024 * 4          # the calibration copy below: 256 MiB read, 256 MiB written
 
 
