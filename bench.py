@@ -115,6 +115,41 @@ def summarize_trace(trace_dir, title, command):
         con.close()
 
 
+def summarize_counters(run_dir, title, command):
+    """Per-kernel averages per dispatch of the SQ counters of a rocprofv3 --pmc run (the re-sort and advect
+    kernels), with the wait fraction SQ_WAIT_ANY / SQ_WAVE_CYCLES and the VALU issue fraction
+    SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES."""
+    import glob
+    import sqlite3
+    acc = {}
+    for db in glob.glob(os.path.join(run_dir, "**", "*results.db"), recursive=True):
+        con = sqlite3.connect(db)
+        q = ("select kernel_name, counter_name, dispatch_id, sum(value), avg(duration) from counters_collection "
+             "group by kernel_name, counter_name, dispatch_id")
+        for name, counter, _, total, dur in con.execute(q):
+            k = acc.setdefault(name, {})
+            k.setdefault(counter, []).append(total)
+            k.setdefault("duration_ns", []).append(dur)
+        con.close()
+    print(f"# rocprofv3 counter summary: {title}")
+    print(f"# command: {command}")
+    print("# per kernel: dispatches, mean duration, mean of each counter per dispatch, wait and VALU-issue fractions")
+    keep = ("k_advect_blk", "k_place", "k_fix", "k_scan", "k_gather")
+    for name in sorted(acc, key=lambda n: -sum(acc[n]["duration_ns"])):
+        if not any(k in name for k in keep):
+            continue
+        c = {k: sum(v) / len(v) for k, v in acc[name].items()}
+        n = max(len(v) for k, v in acc[name].items() if k != "duration_ns")
+        print(f"{name.split('(')[0]}\tdispatches {n}\tduration_us {c.pop('duration_ns') / 1e3:.1f}")
+        for k in sorted(c):
+            print(f"    {k} {c[k]:.0f}")
+        if c.get("SQ_WAVE_CYCLES"):
+            if "SQ_WAIT_ANY" in c:
+                print(f"    wait_fraction {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.3f}")
+            if "SQ_ACTIVE_INST_VALU" in c:
+                print(f"    valu_issue_fraction {c['SQ_ACTIVE_INST_VALU'] / c['SQ_WAVE_CYCLES']:.3f}")
+
+
 def measured_traffic():
     """Bytes per launch of the dominant kernel from the committed counter summary, or None when the summary is
     missing or was taken on other sources."""
@@ -649,6 +684,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="print the counter summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("RUN_DIR", "TITLE", "COMMAND"),
+                    help="print a per-kernel SQ counter summary of a rocprofv3 --pmc run (for profiles/)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "TITLE", "COMMAND"),
                     help="print the per-kernel summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
@@ -657,6 +694,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the particle path has no "

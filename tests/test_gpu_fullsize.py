@@ -271,3 +271,82 @@ def test_octree_full_size_least_squares(L, c3):
     assert np.allclose(xbar[cells][ok], xbar_o[ok], rtol=0, atol=1e-12)
     assert np.allclose(coef[cells][ok], coef_o[ok], rtol=1e-9, atol=1e-11)
     _say(f"  {ok.sum()} sampled cells of {n_cells} compared")
+
+
+def _sampled_compare(g, o, sel, near, pos_tol, prop_tol=None):
+    near_arr = np.array(sorted(near), dtype=np.int64)
+    live_o = set(o["id"].tolist())
+    live_g = set(g["id"][np.isin(g["id"], sel)].tolist())
+    diff = (live_o ^ live_g) - near
+    assert not diff, f"{len(diff)} sampled particles live on one side only, away from faces"
+    common = np.array(sorted(live_o & live_g), dtype=np.uint32)
+    common = common[~np.isin(common.astype(np.int64), near_arr)]
+    gp, op = _by_id(g, common), _by_id(o, common)
+    err = np.abs(g["x"][:, gp] - o["x"][:, op]).max()
+    assert err <= pos_tol, err
+    assert np.array_equal(g["cell"][gp], o["cell"][op])
+    perr = 0.0
+    if prop_tol is not None:
+        a, b = g["prop"][:, gp], o["prop"][:, op]
+        perr = (np.abs(a - b) / np.maximum(1.0, np.abs(b))).max()
+        assert perr <= prop_tol, perr
+    return common.size, err, perr
+
+
+def test_uniform64_property_equations_fused_sampled(L, c2):
+    """The 64^3 RK4 workload with damage and deformation gradient (ten f64 properties), 50 fused steps,
+    FP64 evaluation; 1 particle in 97 followed by the oracle."""
+    from paper_1612_03369_amd.api import Problem
+    cfg = c2
+    _say("case: 64^3 RK4 with the property equations, 50 fused steps, sampled ids")
+    n = cfg["xr"].shape[1]
+    P0 = np.zeros((10, n))
+    P0[0] = 0.1
+    P0[[1, 5, 9]] = 1.0
+    p = Problem(0)
+    p.mesh_uniform(3, cfg["mesh"].n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n, n_prop=10, prop_dtype="float64")
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"], prop=P0)
+    p.set_property_odes(0, 1, 1.0, 0.5)
+    p.advance(cfg["dt"], cfg["steps"], L.PIC_RK4, L.PIC_F64)
+    g = p.numpy()
+    p.close()
+    om = O.OracleMesh.uniform(cfg["mesh"])
+    st, sel = _sample_store(om, cfg, 97, 10)
+    st.prop[:, : st.n] = P0[:, : st.n]
+    near, _ = oracle_run_tracking(om, cfg["U"], cfg["dt"], 4, cfg["steps"], st, odes=(1.0, 0.5, 0, 1))
+    m, err, perr = _sampled_compare(g, st.view(), sel, near, 1e-12, 4e-12)
+    _say(f"  {m} sampled particles, position err {err:.2e}, property err {perr:.2e}")
+
+
+def test_uniform64_time_interpolated_field_fused_sampled(L, c2):
+    """The 64^3 RK4 workload in a field that changes in time (four particle steps per field step, shifted
+    to the next field twice), fused steps, FP64 evaluation; 1 particle in 97 followed by the oracle."""
+    from paper_1612_03369_amd.api import Problem
+    cfg = c2
+    _say("case: 64^3 RK4 in a field changing in time, 12 fused steps over three field steps, sampled ids")
+    nodes = I.uniform_q2_nodes(cfg["mesh"])
+    U = [cfg["U"]] + [I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=20 + k).velocity, nodes))
+                      for k in range(3)]
+    dt = cfg["dt"]
+    p = Problem(0)
+    p.mesh_uniform(3, cfg["mesh"].n)
+    p.set_velocity(U[0])
+    p.allocate(cfg["xr"].shape[1], n_prop=3, prop_dtype="float32")
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+    p.set_velocity_end(U[1], 4 * dt)
+    for k in range(3):
+        p.advance(dt, 4, L.PIC_RK4, L.PIC_F64)
+        if k < 2:
+            p.shift_velocity(U[k + 2], 4 * dt)
+    g = p.numpy()
+    p.close()
+    om = O.OracleMesh.uniform(cfg["mesh"])
+    st, sel = _sample_store(om, cfg, 97, 3)
+    near = set()
+    for k in range(3):
+        nr, _ = oracle_run_tracking(om, U[k], dt, 4, 4, st, tfield=dict(U1=U[k + 1], dt_u=4 * dt, since=0.0))
+        near |= nr
+    m, err, _ = _sampled_compare(g, st.view(), sel, near, 1e-12)
+    _say(f"  {m} sampled particles, position err {err:.2e}")
