@@ -307,7 +307,9 @@ PIC_API pic_status pic_interpolate_points(pic_ctx *ctx, int32_t kind, const doub
 /* Bytes of device workspace for pic_advance_checkpointed with these sizes. */
 PIC_API pic_status pic_adjoint_workspace_bytes(pic_ctx *ctx, int32_t n_steps, int32_t ckpt_every, int64_t *bytes);
 /* Like pic_advance (F64 evaluation), also saving the store every ckpt_every
- * steps into workspace (device, pic_adjoint_workspace_bytes bytes). */
+ * steps into workspace (device, pic_adjoint_workspace_bytes bytes).  Needs a
+ * steady field: PIC_EINVAL while an end field (pic_set_velocity_end) is set,
+ * here and in pic_adjoint. */
 PIC_API pic_status pic_advance_checkpointed(pic_ctx *ctx, double dt, int32_t n_steps, int32_t scheme,
                                     int32_t ckpt_every, void *workspace);
 /* Given dL/dx of the final locations (device [dim][capacity], in the order of
@@ -334,7 +336,9 @@ typedef struct pic_batch pic_batch;
  * launches over a work list of (problem, cell tile) items, replayed from one
  * HIP graph.  tile_cells[0..3] gives the cells per work item for
  * (2D RK2, 2D RK4, 3D RK2, 3D RK4); 0 = default.  The problems' streams are
- * not used; the batch enqueues on `hip_stream`. */
+ * not used; the batch enqueues on `hip_stream`.  Uniform meshes with a steady
+ * field and no property equations only (PIC_EINVAL otherwise); the problems'
+ * settings are taken at creation. */
 PIC_API pic_status pic_batch_create(pic_batch **out, int32_t n, pic_ctx *const *problems, const int32_t tile_cells[4],
                             void *hip_stream);
 /* n_steps steps of every problem with its own dt / scheme (F64 evaluation). */
