@@ -184,8 +184,59 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
     }
 }
 
-// Placement of an unsorted input (prescribed locations): every particle is an
-// arrival in its cell.
+// Runs of equal keys among consecutive lanes of a wavefront (LOST = no key):
+// the lane's run starts at lane `head` and ends before lane `next`.  Every
+// lane of the wavefront must call it.
+struct WaveRun {
+    int lane, head, next;
+};
+__device__ __forceinline__ WaveRun wave_run(uint32_t key)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool starts = lane == 0 || prev != key;
+    const unsigned long long H = __ballot(starts);
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    WaveRun r;
+    r.lane = lane;
+    r.head = 63 - __clzll(H & le);
+    const unsigned long long gt = H & ~le;
+    r.next = gt ? __ffsll((long long)gt) - 1 : 64;
+    return r;
+}
+
+// count[key] += 1 for every lane with a key: one atomic per run.
+__device__ __forceinline__ void wave_count(int32_t *count, uint32_t key)
+{
+    const WaveRun r = wave_run(key);
+    if (key != LOST && r.lane == r.head) atomicAdd(&count[key], r.next - r.head);
+}
+
+// Slot cursor[key]++ for every lane with a key (unspecified for the others):
+// one atomic per run; the lanes of a run take consecutive slots in lane order.
+__device__ __forceinline__ int32_t wave_take(int32_t *cursor, uint32_t key)
+{
+    const WaveRun r = wave_run(key);
+    int32_t base = 0;
+    if (key != LOST && r.lane == r.head) base = atomicAdd(&cursor[key], r.next - r.head);
+    base = __shfl(base, r.head, 64);
+    return base + (r.lane - r.head);
+}
+
+// Wavefront maximum of v, then one atomicMax by lane 0 when it is non-zero.
+__device__ __forceinline__ void wave_max_to(unsigned long long *dst, unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
+}
+
+// Placement of an unsorted input (prescribed locations, particles of another
+// mesh): every particle is an arrival in its cell; consecutive particles with
+// one key take consecutive slots with one atomic.
 __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__restrict__ probs,
                                                           const RangeItem *__restrict__ items, int n_items)
 {
@@ -193,40 +244,49 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
         const RangeItem it = items[w];
         const ProblemDev &P = probs[it.problem];
         const StoreDev cur = P.store[P.cur];
-        const StoreDev nxt = P.store[1 - P.cur];
         const int64_t n = cur.cs[P.mesh.n_cells];
         const int64_t i = it.begin + threadIdx.x;
-        if (i >= n || i >= it.end) continue;
-        const uint32_t key = P.scr.key[P.cur][i];
-        if (key == LOST) continue;
-        P.scr.src[atomicAdd(&P.scr.cursor[key], 1)] = (int32_t)i;
+        const bool mine = i < n && i < it.end;
+        const uint32_t key = mine ? P.scr.key[P.cur][i] : LOST;
+        const int32_t slot = wave_take(P.scr.cursor, key);
+        if (key != LOST) P.scr.src[slot] = (int32_t)i;
     }
 }
 
 // Sort each cell's arrivals by their previous position (= previous global
 // order, since the previous store was sorted by cell); one thread per cell.
 // Up to FIX_LDS arrivals are sorted in LDS (thread t's list interleaved with
-// the others' so that the threads of a wave hit distinct banks); longer lists
-// (rare) in place in global memory.
+// the others' so that the threads of a wave hit distinct banks).  Cells with
+// more (an unsorted input, a coarsened mesh) are sorted afterwards one at a
+// time by the whole workgroup: each arrival's rank among the cell's arrivals
+// (the positions are distinct) is its slot; cells beyond the LDS buffer
+// (very rare) by one thread in global memory.
 constexpr int FIX_LDS = 32;
 __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                int n_items)
 {
     __shared__ int32_t s_v[FIX_LDS * BLOCK];
+    __shared__ int s_nbig;
+    __shared__ int64_t s_big_b[BLOCK];
+    __shared__ int s_big_n[BLOCK];
     for (int wb = blockIdx.x; wb < xcd_span(n_items); wb += gridDim.x) {
         const int w = xcd_item(wb, n_items);
         if (w >= n_items) continue;
         const RangeItem it = items[w];
         const ProblemDev &P = probs[it.problem];
         const int64_t K = it.begin + threadIdx.x;
-        if (K >= it.end || K >= P.mesh.n_cells) continue;
+        const bool mine = K < it.end && K < P.mesh.n_cells;
         const StoreDev nxt = P.store[1 - P.cur];
-        const int64_t b = (int64_t)nxt.cs[K] + P.scr.n_stay[K];
-        const int64_t e = nxt.cs[K + 1];
-        const int n = (int)(e - b);
-        if (n < 2) continue;
-        auto a = (gptr_mut<int32_t>)(P.scr.src + b);
-        if (n <= FIX_LDS) {
+        const int64_t b = mine ? (int64_t)nxt.cs[K] + P.scr.n_stay[K] : 0;
+        const int n = mine ? (int)(nxt.cs[K + 1] - b) : 0;
+        if (threadIdx.x == 0) s_nbig = 0;
+        __syncthreads();
+        if (n > FIX_LDS) {
+            const int slot = atomicAdd(&s_nbig, 1);
+            s_big_b[slot] = b;
+            s_big_n[slot] = n;
+        } else if (n >= 2) {
+            auto a = (gptr_mut<int32_t>)(P.scr.src + b);
             int32_t *v = s_v + threadIdx.x;
 #pragma unroll
             for (int q = 0; q < FIX_LDS; ++q)
@@ -241,17 +301,38 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
                 v[(r + 1) * BLOCK] = x;
             }
             for (int q = 0; q < n; ++q) a[q] = v[q * BLOCK];
-        } else {
-            for (int q = 1; q < n; ++q) {         // rare: many arrivals in one cell
-                const int32_t x = a[q];
-                int r = q - 1;
-                while (r >= 0 && a[r] > x) {
-                    a[r + 1] = a[r];
-                    --r;
+        }
+        __syncthreads();
+        const int nbig = s_nbig;
+        for (int c = 0; c < nbig; ++c) {
+            const int nn = s_big_n[c];
+            auto a = (gptr_mut<int32_t>)(P.scr.src + s_big_b[c]);
+            if (2 * nn <= FIX_LDS * BLOCK) {
+                int32_t *v = s_v, *o = s_v + nn;
+                for (int q = threadIdx.x; q < nn; q += BLOCK) v[q] = a[q];
+                __syncthreads();
+                for (int q = threadIdx.x; q < nn; q += BLOCK) {
+                    const int32_t x = v[q];
+                    int r = 0;
+                    for (int j = 0; j < nn; ++j) r += v[j] < x;
+                    o[r] = x;
                 }
-                a[r + 1] = x;
+                __syncthreads();
+                for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = o[q];
+                __syncthreads();
+            } else if (threadIdx.x == 0) {
+                for (int q = 1; q < nn; ++q) {
+                    const int32_t x = a[q];
+                    int r = q - 1;
+                    while (r >= 0 && a[r] > x) {
+                        a[r + 1] = a[r];
+                        --r;
+                    }
+                    a[r + 1] = x;
+                }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -377,12 +458,13 @@ __global__ __launch_bounds__(BLOCK) void k_transfer_in(const ProblemDev *src_pro
     const int64_t scap = S.cap, cap = P.cap;
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p == 0) atomicMax(&P.scr.next_id[1], S.scr.next_id[0]);
-    if (p >= n) return;
-    double x[3], t[3];
-    for (int a = 0; a < D; ++a) x[a] = src.x[a * scap + p];
+    const bool mine = p < n;           // every lane stays for the wavefront atomics
+    double x[3] = {0.0, 0.0, 0.0}, t[3];
+    if (mine)
+        for (int a = 0; a < D; ++a) x[a] = src.x[a * scap + p];
     int32_t K = -1;
     LocStats ls = {0, 0, 0, 0};
-    bool ok = in_box_domain<D>(m, x);
+    bool ok = mine && in_box_domain<D>(m, x);
     if (ok) {
         if constexpr (KIND == MESH_UNIFORM) {
             ok = locate<D, KIND>(m, x, 0, K, t, ls);
@@ -393,21 +475,26 @@ __global__ __launch_bounds__(BLOCK) void k_transfer_in(const ProblemDev *src_pro
             ok = global_search_displaced<D>(m, x, K, t, ls);
         }
     }
-    for (int a = 0; a < D; ++a) {
-        cur.x[a * cap + p] = x[a];
-        cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+    uint32_t id = 0;
+    if (mine) {
+        for (int a = 0; a < D; ++a) {
+            cur.x[a * cap + p] = x[a];
+            cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+        }
+        cur.cell[p] = -1;
+        id = src.id[p];
+        cur.id[p] = id;
+        for (int j = 0; j < P.n_prop; ++j) {
+            if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = ((const double *)src.prop)[j * scap + p];
+            else ((float *)cur.prop)[j * cap + p] = ((const float *)src.prop)[j * scap + p];
+        }
+        P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
     }
-    cur.cell[p] = -1;
-    const uint32_t id = src.id[p];
-    cur.id[p] = id;
-    for (int j = 0; j < P.n_prop; ++j) {
-        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = ((const double *)src.prop)[j * scap + p];
-        else ((float *)cur.prop)[j * cap + p] = ((const float *)src.prop)[j * scap + p];
-    }
-    P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
-    if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
-    else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
-    atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], (unsigned long long)id + 1ull);
+    wave_count(P.scr.n_arrive, ok ? (uint32_t)K : LOST);
+    const int lost = wave_sum((int)(mine && !ok));
+    if ((threadIdx.x & 63) == 0 && lost)
+        atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], (unsigned long long)lost);
+    wave_max_to(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], mine ? (unsigned long long)id + 1ull : 0ull);
 }
 
 template <int D, int KIND>
@@ -420,12 +507,13 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
     const StoreDev cur = P.store[P.cur];
     const int64_t cap = P.cap;
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= n) return;
-    double x[3], t[3];
-    for (int a = 0; a < D; ++a) x[a] = x_in[a * n + p];
+    const bool mine = p < n;           // every lane stays for the wavefront atomics
+    double x[3] = {0.0, 0.0, 0.0}, t[3];
+    if (mine)
+        for (int a = 0; a < D; ++a) x[a] = x_in[a * n + p];
     int32_t K = -1;
     LocStats ls = {0, 0, 0, 0};
-    bool ok = in_box_domain<D>(m, x);
+    bool ok = mine && in_box_domain<D>(m, x);
     if (ok) {
         if constexpr (KIND == MESH_UNIFORM) {
             ok = locate<D, KIND>(m, x, 0, K, t, ls);
@@ -436,22 +524,28 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
             ok = global_search_displaced<D>(m, x, K, t, ls);
         }
     }
-    for (int a = 0; a < D; ++a) {
-        cur.x[a * cap + p] = x[a];
-        cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+    uint32_t id = 0;
+    if (mine) {
+        for (int a = 0; a < D; ++a) {
+            cur.x[a * cap + p] = x[a];
+            cur.xr[a * cap + p] = ok ? t[a] : 0.0;
+        }
+        cur.cell[p] = -1;
+        id = ids[p];
+        cur.id[p] = id;
+        for (int j = 0; j < P.n_prop; ++j) {
+            double v = prop_init == 1 ? x[j % D]
+                                      : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
+            if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
+            else ((float *)cur.prop)[j * cap + p] = (float)v;
+        }
+        P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
     }
-    cur.cell[p] = -1;
-    cur.id[p] = ids[p];
-    for (int j = 0; j < P.n_prop; ++j) {
-        double v = prop_init == 1 ? x[j % D]
-                                  : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
-        if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
-        else ((float *)cur.prop)[j * cap + p] = (float)v;
-    }
-    P.scr.key[P.cur][p] = ok ? (uint32_t)K : LOST;
-    if (ok) atomicAdd(&P.scr.n_arrive[K], 1);
-    else atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], 1ull);
-    atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], (unsigned long long)ids[p] + 1ull);
+    wave_count(P.scr.n_arrive, ok ? (uint32_t)K : LOST);
+    const int lost = wave_sum((int)(mine && !ok));
+    if ((threadIdx.x & 63) == 0 && lost)
+        atomicAdd(&P.scr.stats[(blockIdx.x % STAT_STRIPES) * ST_COUNT + ST_LOST], (unsigned long long)lost);
+    wave_max_to(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], mine ? (unsigned long long)id + 1ull : 0ull);
 }
 
 // ===========================================================================
