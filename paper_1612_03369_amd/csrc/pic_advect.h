@@ -721,6 +721,10 @@ template <int D, typename T> struct BlkWaves {
 #define PIC_BLK_PREFETCH 2          // 1: load the next particle's state while advancing this one; 2: also its gather source one step earlier
 #endif
 constexpr int ADV_BLOCK = PIC_ADV_THREADS;
+#ifndef PIC_BLK_EARLY
+#define PIC_BLK_EARLY 1             // fused kernels: read id and the first properties before the step (0: after it)
+#endif
+constexpr int PF_PROPS = 4;         // single-precision properties carried in registers by the fused kernels
 template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED, bool ODE = false, bool TI = false>
 __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE || TI ? 1 : BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
                                                                       const BlockItem *__restrict__ work, int n_work)
@@ -853,14 +857,46 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE |
         }
         // stage the window (its loads overlap the first fetch); nodes beyond
         // the mesh are never read (stage points are clamped to mesh cells)
-        // and are left unset
-        for (int q = threadIdx.x; q < Sh::NODES; q += ADV_BLOCK) {
-            const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
-            const int gi = 2 * (bi.i0 - 1) + wx, gj = 2 * (bi.j0 - 1) + wy, gk = D == 3 ? 2 * (bi.k0 - 1) + wz : 0;
-            if (gi >= 0 && gi < m.nnx && gj >= 0 && gj < m.nny && gk >= 0 && gk < (D == 3 ? m.nnz : 1)) {
-                const int64_t g = gi + (int64_t)m.nnx * (gj + (int64_t)m.nny * gk);
-                s_w[q] = Ug[g];
-                if constexpr (TI) s_w[Sh::NODES + q] = Ug1[g];
+        // and are left unset.  Every thread requests all its nodes before it
+        // stores the first one to LDS, so that the loads are in flight
+        // together (entries beyond the mesh load node 0 and are dropped).
+        {
+            constexpr int NQ = (Sh::NODES + ADV_BLOCK - 1) / ADV_BLOCK;
+            const int nnx = m.nnx, nny = m.nny, nnz = D == 3 ? m.nnz : 1;
+            using E = decltype(V{}.x);
+            E a0[NQ], a1[NQ], a2[NQ], b0_[TI ? NQ : 1], b1_[TI ? NQ : 1], b2_[TI ? NQ : 1];
+            uint32_t ok = 0;
+            // (the index arithmetic stays inside the work-item loop: hoisted
+            // out of it, its NQ results would be spilled)
+            int tq = threadIdx.x;
+            asm volatile("" : "+v"(tq));
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tq + u * ADV_BLOCK;
+                const int wx = q % Sh::WX, wy = (q / Sh::WX) % Sh::WY, wz = q / (Sh::WX * Sh::WY);
+                const int gi = 2 * (bi.i0 - 1) + wx, gj = 2 * (bi.j0 - 1) + wy, gk = D == 3 ? 2 * (bi.k0 - 1) + wz : 0;
+                const bool in = q < Sh::NODES && gi >= 0 && gi < nnx && gj >= 0 && gj < nny && gk >= 0 && gk < nnz;
+                const int64_t g = in ? gi + (int64_t)nnx * (gj + (int64_t)nny * gk) : 0;
+                ok |= (uint32_t)in << u;
+                const V v = Ug[g];
+                a0[u] = v.x;
+                a1[u] = v.y;
+                a2[u] = nv_z(v);
+                if constexpr (TI) {
+                    const V v1 = Ug1[g];
+                    b0_[u] = v1.x;
+                    b1_[u] = v1.y;
+                    b2_[u] = nv_z(v1);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tq + u * ADV_BLOCK;
+                if ((ok >> u) & 1u) {
+                    s_w[q] = node_of<V>(a0[u], a1[u], a2[u]);
+                    if constexpr (TI) s_w[Sh::NODES + q] = node_of<V>(b0_[u], b1_[u], b2_[u]);
+                }
             }
         }
         for (int q = threadIdx.x; q < Sh::CELLS; q += ADV_BLOCK) s_cnt[q] = 0;
@@ -881,6 +917,26 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE |
             } else if (PIC_BLK_PREFETCH && f + ADV_BLOCK < total) {
                 fetch(f + ADV_BLOCK);
             }
+            // The id and the first single-precision properties of the particle
+            // are read now: their latency then hides behind the step, whereas a
+            // load issued after the step's stores would wait for those stores
+            // too (one memory counter serves loads and stores).  Loads past the
+            // last property re-read the first one, so that no load sits behind
+            // a branch.
+            uint32_t idv = 0;
+            uint32_t pv[PF_PROPS];
+            const int npf = FUSED && PIC_BLK_EARLY && !P.prop_f64 ? min(P.n_prop, PF_PROPS) : 0;
+            auto read_early = [&]() {
+                if constexpr (FUSED && PIC_BLK_EARLY) {
+                    idv = cur.id[sidx];
+                    if (npf > 0) {
+#pragma unroll
+                        for (int j = 0; j < PF_PROPS; ++j)
+                            pv[j] = ((const uint32_t PIC_G *)cur.prop)[(j < npf ? j : 0) * cap + sidx];
+                    }
+                }
+            };
+            read_early();
             bool near = false;
             uint32_t key;
             double Pp[1 + D * D];
@@ -902,13 +958,24 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE |
                 }
             }
             if constexpr (FUSED) {
-                out.id[p] = cur.id[sidx];
                 out.cell[p] = K;
-                if (P.prop_f64) {
-                    for (int j = 0; j < P.n_prop; ++j)
-                        ((double *)out.prop)[j * cap + p] = ((const double *)cur.prop)[j * cap + sidx];
+                if constexpr (PIC_BLK_EARLY) {
+                    out.id[p] = idv;
+#pragma unroll
+                    for (int j = 0; j < PF_PROPS; ++j)
+                        if (j < npf) ((uint32_t PIC_G *)out.prop)[j * cap + p] = pv[j];
                 } else {
-                    for (int j = 0; j < P.n_prop; ++j)
+                    out.id[p] = cur.id[sidx];
+                }
+                // the rest one by one (the integrated properties are written below)
+                if (P.prop_f64) {
+                    for (int j = npf; j < P.n_prop; ++j) {
+                        if constexpr (ODE)
+                            if (j == P.ode_dmg || (unsigned)(j - P.ode_F) < (unsigned)(D * D)) continue;
+                        ((double *)out.prop)[j * cap + p] = ((const double *)cur.prop)[j * cap + sidx];
+                    }
+                } else {
+                    for (int j = npf; j < P.n_prop; ++j)
                         ((float *)out.prop)[j * cap + p] = ((const float *)cur.prop)[j * cap + sidx];
                 }
             }

@@ -16,6 +16,9 @@ constexpr double NEAR_TOL = 1e-10;   // near-face band in reference coordinates
 constexpr int BLOCK = 256;           // threads per workgroup of the per-tile kernels
 constexpr int MAX_TILE = 1024;       // cells per work item (LDS arrays are sized by it)
 constexpr int MAX_NBR = 64;          // vertex neighbours of one cell (octree upper bound)
+#ifndef PIC_EVAL_BATCH
+#define PIC_EVAL_BATCH 1                // 3D evaluation: load a plane of nodes before summing it
+#endif
 #ifndef PIC_EVAL_UNROLL
 #define PIC_EVAL_UNROLL 3               // unroll of the outermost sum-factorisation loop
 #endif
@@ -112,6 +115,18 @@ __device__ __forceinline__ float nv_z(const float4 &v) { return v.z; }
 __device__ __forceinline__ double nv_z(const double4 &v) { return v.z; }
 __device__ __forceinline__ float nv_z(const float2 &) { return 0.f; }
 __device__ __forceinline__ double nv_z(const double2 &) { return 0.0; }
+// node value from its components (z ignored in 2D; the fourth lane of a 3D node is padding)
+template <typename V, typename E> __device__ __forceinline__ V node_of(E x, E y, E z)
+{
+    V v;
+    v.x = x;
+    v.y = y;
+    if constexpr (sizeof(V) == 4 * sizeof(E)) {
+        v.z = z;
+        v.w = E(0);
+    }
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // rounding-pinned building blocks of the sum-factorised evaluation: every
@@ -385,14 +400,36 @@ __device__ __forceinline__ void eval_q2_at(Ptr U, I base, I sy, I sz, const doub
         T a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll PIC_EVAL_UNROLL
         for (int c = 0; c < 3; ++c) {
+#if PIC_EVAL_BATCH
+            // the nine nodes of plane c are all requested before the first is
+            // used, so that their load latencies overlap (the scheduler would
+            // otherwise interleave loads and uses to save registers)
+            T vx[3][3], vy[3][3], vz[3][3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const auto w = U[base + nnx * b + sz * c + i];
+                    vx[b][i] = (T)w.x;
+                    vy[b][i] = (T)w.y;
+                    vz[b][i] = (T)w.z;
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#endif
             T r0 = 0, r1 = 0, r2 = 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
+#if PIC_EVAL_BATCH
+                r0 = fma_t(lb[b], row3(la, vx[b][0], vx[b][1], vx[b][2]), r0);
+                r1 = fma_t(lb[b], row3(la, vy[b][0], vy[b][1], vy[b][2]), r1);
+                r2 = fma_t(lb[b], row3(la, vz[b][0], vz[b][1], vz[b][2]), r2);
+#else
                 const I r = base + nnx * b + sz * c;
                 const auto v0 = U[r], v1 = U[r + 1], v2 = U[r + 2];
                 r0 = fma_t(lb[b], row3(la, (T)v0.x, (T)v1.x, (T)v2.x), r0);
                 r1 = fma_t(lb[b], row3(la, (T)v0.y, (T)v1.y, (T)v2.y), r1);
                 r2 = fma_t(lb[b], row3(la, (T)v0.z, (T)v1.z, (T)v2.z), r2);
+#endif
             }
             a0 = fma_t(lc[c], r0, a0);
             a1 = fma_t(lc[c], r1, a1);
@@ -971,13 +1008,23 @@ __device__ __forceinline__ int xcd_item(int b, int n) { return (b % N_XCD) * ((n
 // ---------------------------------------------------------------------------
 // Exclusive scan of 0/1 flags over a 256-thread workgroup; returns the prefix
 // and the workgroup total.  s_wave must hold BLOCK/64 ints.
+// Workgroup barrier that orders LDS accesses only: global memory operations
+// issued before it need not have completed (for kernels whose workgroups do
+// not read back their own global writes).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int block_scan_flags(int flag, int *s_wave, int &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long m = __ballot(flag);
     const int pre = __popcll(m & ((1ull << lane) - 1ull));
     if (lane == 0) s_wave[wid] = __popcll(m);
-    __syncthreads();
+    lds_barrier();
     int off = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) {
@@ -985,7 +1032,7 @@ __device__ __forceinline__ int block_scan_flags(int flag, int *s_wave, int &tota
         off += (w < wid) ? c : 0;
         tot += c;
     }
-    __syncthreads();
+    lds_barrier();
     total = tot;
     return off + pre;
 }

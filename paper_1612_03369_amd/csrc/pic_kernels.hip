@@ -157,29 +157,34 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
             key_n = keys[p0 + threadIdx.x];
             K_n = cur.cell[p0 + threadIdx.x];
         }
+        // The rounds synchronise through LDS only (the src writes are read by
+        // later kernels), and an arrival takes its slot at the start of the
+        // round, so that the atomic's round trip overlaps the round's scan.
         int carry = 0;
         for (int base = p0; base < p1; base += BLOCK) {
             const int i = base + threadIdx.x;
             const bool active = i < p1;
             const uint32_t key = key_n;
             const int K = K_n;
+            const int stay = active && key == (uint32_t)K;
+            int32_t slot;                    // set (and read) for arrivals only
+            if (active && key != LOST && !stay) slot = atomicAdd(&P.scr.cursor[key], 1);
             if (i + BLOCK < p1) {
                 key_n = keys[i + BLOCK];
                 K_n = cur.cell[i + BLOCK];
             }
-            const int stay = active && key == (uint32_t)K;
             int total;
             const int pre = block_scan_flags(stay, s_wave, total);
             const int Pi = carry + pre;
             const int kloc = K - c0;
             if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
-            __syncthreads();
+            lds_barrier();
             if (active && key != LOST) {
-                const int64_t dst = stay ? (int64_t)s_ncs[kloc] + (Pi - s_base[kloc]) : atomicAdd(&P.scr.cursor[key], 1);
+                const int32_t dst = stay ? s_ncs[kloc] + (Pi - s_base[kloc]) : slot;
                 P.scr.src[dst] = i;
             }
             carry += total;
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -288,9 +293,20 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
         } else if (n >= 2) {
             auto a = (gptr_mut<int32_t>)(P.scr.src + b);
             int32_t *v = s_v + threadIdx.x;
+            // eight loads in flight before the first is stored to LDS (loads
+            // past the end re-read the cell's last arrival)
 #pragma unroll
-            for (int q = 0; q < FIX_LDS; ++q)
-                if (q < n) v[q * BLOCK] = a[q];
+            for (int q0 = 0; q0 < FIX_LDS; q0 += 8) {
+                if (q0 < n) {
+                    int32_t r[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) r[q] = a[min(q0 + q, n - 1)];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q0 + q < n) v[(q0 + q) * BLOCK] = r[q];
+                }
+            }
             for (int q = 1; q < n; ++q) {
                 const int32_t x = v[q * BLOCK];
                 int r = q - 1;
