@@ -282,8 +282,13 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
         const int64_t K = it.begin + threadIdx.x;
         const bool mine = K < it.end && K < P.mesh.n_cells;
         const StoreDev nxt = P.store[1 - P.cur];
-        const int64_t b = mine ? (int64_t)nxt.cs[K] + P.scr.n_stay[K] : 0;
-        const int n = mine ? (int)(nxt.cs[K + 1] - b) : 0;
+        int64_t b = 0;
+        int n = 0;
+        if (mine) {                              // the three loads in flight together
+            const int32_t c0 = nxt.cs[K], c1 = nxt.cs[K + 1], ns = P.scr.n_stay[K];
+            b = (int64_t)c0 + ns;
+            n = (int)(c1 - b);
+        }
         if (threadIdx.x == 0) s_nbig = 0;
         __syncthreads();
         if (n > FIX_LDS) {
