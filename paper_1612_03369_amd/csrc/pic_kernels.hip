@@ -260,7 +260,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 
 // Sort each cell's arrivals by their previous position (= previous global
 // order, since the previous store was sorted by cell); one thread per cell.
-// Up to FIX_LDS arrivals are sorted in LDS (thread t's list interleaved with
+// Up to FIX_LDS arrivals are ranked in LDS (thread t's list interleaved with
 // the others' so that the threads of a wave hit distinct banks).  Cells with
 // more (an unsorted input, a coarsened mesh) are sorted afterwards one at a
 // time by the whole workgroup: each arrival's rank among the cell's arrivals
@@ -312,16 +312,16 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
                         if (q0 + q < n) v[(q0 + q) * BLOCK] = r[q];
                 }
             }
-            for (int q = 1; q < n; ++q) {
+            // each slot's rank among the cell's arrivals (the positions are
+            // distinct) is where it goes: n^2 independent LDS reads instead of
+            // an insertion sort's chain of dependent ones
+            for (int q = 0; q < n; ++q) {
                 const int32_t x = v[q * BLOCK];
-                int r = q - 1;
-                while (r >= 0 && v[r * BLOCK] > x) {
-                    v[(r + 1) * BLOCK] = v[r * BLOCK];
-                    --r;
-                }
-                v[(r + 1) * BLOCK] = x;
+                int r = 0;
+#pragma unroll 8
+                for (int j = 0; j < n; ++j) r += v[j * BLOCK] < x;
+                a[r] = x;
             }
-            for (int q = 0; q < n; ++q) a[q] = v[q * BLOCK];
         }
         __syncthreads();
         const int nbig = s_nbig;
