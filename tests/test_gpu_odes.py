@@ -191,3 +191,54 @@ def test_property_odes_argument_checks(L):
     p.set_property_odes(4, 0, 1.0, 1.0)
     p.set_property_odes(-1, -1)
     p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_property_odes_with_carried_properties(L, prec):
+    """Integrated properties among plain carried ones (one before, one after):
+    the fused kernels copy the carried ones and write the integrated ones.
+    Fused = single steps bit for bit; the carried values are the seeded ones;
+    the integrated values equal those of a run that holds only them."""
+    from paper_1612_03369_amd.api import Problem
+    _say(f"case: property equations with carried properties, prec={prec}")
+    dim, n, scheme, steps = 3, 8, 4, 5
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(dim, seed=1500).velocity, I.uniform_q2_nodes(mesh)))
+    counts = np.random.default_rng(1501).integers(0, 9, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=1502)
+    npart = xr.shape[1]
+    P_ode = _initial_props(dim, npart, 77)
+    extra = np.random.default_rng(1503).standard_normal((2, npart))
+    P_all = np.concatenate([extra[:1], P_ode, extra[1:]])       # carried, damage, F, carried
+    dt = 0.6 / n
+
+    def run(prop, dmg, fdef, fused):
+        p = Problem(0)
+        p.mesh_uniform(dim, mesh.n[:dim])
+        p.set_velocity(U)
+        p.allocate(npart, n_prop=prop.shape[0], prop_dtype="float64")
+        p.seed_reference(counts, xr, ids, prop=prop)
+        p.set_property_odes(dmg, fdef, ALPHA, BETA)
+        if fused:
+            p.advance(dt, steps, scheme, prec)
+        else:
+            for _ in range(steps):
+                p.advance(dt, 1, scheme, prec)
+        out = p.numpy()
+        p.close()
+        return out
+
+    g = run(P_all, 1, 2, True)
+    g1 = run(P_all, 1, 2, False)
+    for k in ("x", "xr", "cell", "id", "prop"):
+        assert np.array_equal(g[k], g1[k]), k
+    # carried properties: the seeded values of each surviving id
+    order = np.argsort(ids)
+    pos = order[np.searchsorted(ids[order], g["id"])]
+    assert np.array_equal(g["prop"][0], extra[0][pos])
+    assert np.array_equal(g["prop"][11], extra[1][pos])
+    # integrated properties: as in a run with the integrated ones alone
+    h = run(P_ode, 0, 1, True)
+    assert np.array_equal(g["id"], h["id"]) and np.array_equal(g["x"], h["x"])
+    assert np.array_equal(g["prop"][1:11], h["prop"])
+    _say(f"  {g['id'].size} particles after {steps} fused steps: carried and integrated properties as expected")
