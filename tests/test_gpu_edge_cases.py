@@ -104,3 +104,45 @@ def test_transfer_of_an_empty_store(L):
     assert b.stats()["live"] == 0
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("n_prop,dtype", [(0, "float32"), (1, "float32"), (4, "float32"), (6, "float32"),
+                                          (2, "float64")])
+def test_fused_steps_carry_any_number_of_properties(L, n_prop, dtype):
+    """The fused kernels carry up to four single-precision properties in
+    registers and copy the rest (and double-precision ones) one by one: for
+    every count, fused = single steps bit for bit, and each surviving particle
+    keeps its seeded values."""
+    from paper_1612_03369_amd.api import Problem
+    _say(f"case: fused steps with {n_prop} {dtype} properties")
+    dim, n, steps = 3, 8, 4
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(dim, seed=1600).velocity, I.uniform_q2_nodes(mesh)))
+    counts = np.random.default_rng(1601).integers(0, 9, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=1602)
+    npart = xr.shape[1]
+    prop = np.random.default_rng(1603).standard_normal((n_prop, npart)).astype(dtype)
+    dt = 0.6 / n
+    outs = []
+    for fused in (True, False):
+        p = Problem(0)
+        p.mesh_uniform(dim, mesh.n[:dim])
+        p.set_velocity(U)
+        p.allocate(npart, n_prop=n_prop, prop_dtype=dtype)
+        p.seed_reference(counts, xr, ids, prop=prop if n_prop else None, init_position=False)
+        if fused:
+            p.advance(dt, steps, 4, 1)
+        else:
+            for _ in range(steps):
+                p.advance(dt, 1, 4, 1)
+        outs.append(p.numpy())
+        p.close()
+    g, g1 = outs
+    keys = ("x", "xr", "cell", "id") + (("prop",) if n_prop else ())
+    for k in keys:
+        assert np.array_equal(g[k], g1[k]), k
+    if n_prop:
+        order = np.argsort(ids)
+        pos = order[np.searchsorted(ids[order], g["id"])]
+        assert np.array_equal(g["prop"], prop[:, pos])
+    _say(f"  {g['id'].size} particles after {steps} fused steps")
