@@ -275,6 +275,8 @@ def run_main(args):
         b.copy_(a)
     torch.cuda.synchronize()
     line["copy_gbs"] = 2 * a.numel() * 4 * 10 / (time.perf_counter() - t) / 1e9
+    # the dominant kernel's algorithmic rate against what a plain device copy reaches on this GPU
+    line["roofline"]["frac_of_copy"] = line["roofline"]["achieved"] / line["copy_gbs"]
     del a, b
     p.close()
 
