@@ -721,12 +721,15 @@ template <int D, typename T> struct BlkWaves {
 #define PIC_BLK_PREFETCH 2          // 1: load the next particle's state while advancing this one; 2: also its gather source one step earlier
 #endif
 constexpr int ADV_BLOCK = PIC_ADV_THREADS;
+#ifndef PIC_ODE_WAVES
+#define PIC_ODE_WAVES 2             // single-precision kernels with the property equations: registers for two waves per SIMD
+#endif
 #ifndef PIC_BLK_EARLY
 #define PIC_BLK_EARLY 1             // fused kernels: read id and the first properties before the step (0: after it)
 #endif
 constexpr int PF_PROPS = 4;         // single-precision properties carried in registers by the fused kernels
 template <int D, int S, typename T, int BX, int BY, int BZ, bool FUSED, bool ODE = false, bool TI = false>
-__global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE || TI ? 1 : BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
+__global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ? (sizeof(T) == 4 ? PIC_ODE_WAVES : 1) : TI ? 1 : BlkWaves<D, T>::value))) void k_advect_blk(const ProblemDev *__restrict__ probs,
                                                                       const BlockItem *__restrict__ work, int n_work)
 {
     using Sh = BlockShape<D, BX, BY, BZ>;

@@ -934,12 +934,28 @@ __device__ __forceinline__ void grad_q2_at(Ptr U, I base, I sy, I sz, const doub
 #pragma unroll
         for (int r = 0; r < 3; ++r) g[c][r] = T(0);
 #pragma unroll 1
-    for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
+    for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3) {
+#if PIC_EVAL_BATCH
+        // the plane's nine nodes are requested before the first is used
+        T px[3][3], py[3][3], pz[3][3];
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const auto v = U[base + a + sy * b + sz * c3];
+                px[b][a] = (T)nv_x(v);
+                py[b][a] = (T)nv_y(v);
+                pz[b][a] = D == 3 ? (T)nv_z(v) : T(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#endif
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+#if !PIC_EVAL_BATCH
+                const auto v = U[base + a + sy * b + sz * c3];
+#endif
                 T w[3];
                 if constexpr (D == 2) {
                     w[0] = dl[0][a] * l[1][b];
@@ -950,12 +966,17 @@ __device__ __forceinline__ void grad_q2_at(Ptr U, I base, I sy, I sz, const doub
                     w[1] = l[0][a] * dl[1][b] * l[2][c3];
                     w[2] = l[0][a] * l[1][b] * dl[2][c3];
                 }
+#if PIC_EVAL_BATCH
+                const T vc[3] = {px[b][a], py[b][a], pz[b][a]};
+#else
                 const T vc[3] = {(T)nv_x(v), (T)nv_y(v), D == 3 ? (T)nv_z(v) : T(0)};
+#endif
 #pragma unroll
                 for (int c = 0; c < D; ++c)
 #pragma unroll
                     for (int r = 0; r < D; ++r) g[c][r] = fma_t(vc[c], w[r], g[c][r]);
             }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
