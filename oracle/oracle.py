@@ -101,6 +101,8 @@ def lib():
             L.orc_adjoint.restype = C.c_double
             L.orc_adjoint.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_int64,
                                       P, P, P, P, P, P, P]
+            L.orc_seed_per_cell.restype = C.c_int
+            L.orc_seed_per_cell.argtypes = [P, P, C.c_uint64, C.c_uint32, C.c_int, P]
             L.orc_octree_fine_table.restype = C.c_int
             L.orc_octree_fine_table.argtypes = [C.c_int64, C.c_int, P, P, P]
             _lib = L
@@ -409,6 +411,22 @@ def stable_sort_perm(n_cells, old_cell, key):
     cs = np.zeros(n_cells + 1, np.int64)
     m = lib().orc_sort_perm(int(n_cells), n, _p(old_cell), _p(key), _p(perm), _p(cs))
     return perm[:m], cs
+
+
+def seed_per_cell(mesh: OracleMesh, counts, seed_, first_id, n_prop, cap=None, init_position=True):
+    """Reference-local generation with the counter hash (Sec. 2.2, remark on local generation):
+    particle j of cell K at xhat_a = uniform01(seed, 2^64 - 1, K, j, a), ids first_id + position."""
+    counts = np.ascontiguousarray(counts, np.int32)
+    n = int(counts.sum())
+    st = OracleStore(mesh.dim, cap or max(n, 1), n_prop)
+    rc = lib().orc_seed_per_cell(C.byref(mesh.c), _p(counts), int(seed_), int(first_id), int(init_position),
+                                 C.byref(st.c))
+    if rc != 0:
+        raise ValueError("capacity too small" if rc == -1 else "negative count")
+    cs = np.zeros(mesh.n_cells + 1, np.int64)
+    cs[1:] = np.cumsum(counts)
+    st.cell_start = cs
+    return st
 
 
 def population(mesh: OracleMesh, st: OracleStore, pmin, pmax, seed_, step_, next_id):

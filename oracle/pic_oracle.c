@@ -926,6 +926,41 @@ double orc_uniform01(uint64_t seed, uint64_t step, uint64_t cell, uint64_t slot,
     return (double)(h >> 11) * (1.0 / 9007199254740992.0);
 }
 
+/* Reference-local generation with the counter hash (Sec. 2.2, remark on
+ * generating particles in the reference cell): particle j of cell K, listed
+ * cell by cell, gets xhat_a = uniform01(seed, 2^64 - 1, K, j, a) (the step slot
+ * holds the all-ones tag of this stream), x = Phi_K(xhat), id = first_id +
+ * its position in the listing, property j = coordinate j mod dim of x if
+ * init_position. */
+int orc_seed_per_cell(const orc_mesh *m, const int32_t *counts, uint64_t seed, uint32_t first_id, int init_position,
+                      orc_store *s)
+{
+    int d = m->dim;
+    int64_t nc = orc_n_cells(m), p = 0;
+    for (int64_t K = 0; K < nc; ++K) {
+        if (counts[K] < 0) return -2;
+        p += counts[K];
+    }
+    if (p > s->cap) return -1;
+    p = 0;
+    for (int64_t K = 0; K < nc; ++K)
+        for (int32_t j = 0; j < counts[K]; ++j, ++p) {
+            double t[3], x[3];
+            for (int a = 0; a < d; ++a) t[a] = orc_uniform01(seed, ~0ull, (uint64_t)K, (uint64_t)j, (uint64_t)a);
+            map_to_real(m, K, t, x, NULL);
+            for (int a = 0; a < d; ++a) {
+                s->x[a * s->cap + p] = x[a];
+                s->xr[a * s->cap + p] = t[a];
+            }
+            s->cell[p] = (int32_t)K;
+            s->id[p] = first_id + (uint32_t)p;
+            if (init_position)
+                for (int q = 0; q < s->n_prop; ++q) s->prop[q * s->cap + p] = x[q % d];
+        }
+    s->n = p;
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Metropolis-Hastings generation (Sec. 2.2)                           */
 /* ------------------------------------------------------------------ */

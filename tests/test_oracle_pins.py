@@ -1114,3 +1114,71 @@ def test_transfer_to_coarsened_cells_and_back():
     pos = {int(i): k for k, i in enumerate(back.id[: back.n])}
     idx = np.array([pos[int(i)] for i in st.id[: st.n]])
     assert np.abs(back.xr[:, idx] - st.xr[:, : st.n]).max() <= 4e-15
+
+
+# ----------------------------------------------------------------------------
+# reference-local generation with the counter hash (Sec. 2.2)
+# ----------------------------------------------------------------------------
+_M64 = 0xFFFFFFFFFFFFFFFF
+
+
+def _sm64(z):
+    """SplitMix64 output for state z, written from its published definition (Steele, Lea, Flood 2014)."""
+    z = (z + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def _u01(*words):
+    h = _sm64(words[0])
+    for w in words[1:]:
+        h = _sm64(h ^ w)
+    return (h >> 11) / 9007199254740992.0
+
+
+def test_python_splitmix64_matches_published_values():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    state = 0
+    for v in vals:
+        assert _sm64(state) == v
+        state = (state + 0x9E3779B97F4A7C15) & _M64
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_seed_per_cell_counter_stream(dim):
+    """Particle j of cell K sits at xhat_a = u(seed, 2^64-1, K, j, a) with u the SplitMix64 chain
+    recomputed here in Python; x = Phi_K(xhat); ids first_id + listing position; properties = x;
+    the draws are uniform on [0,1)."""
+    n = (7, 5, 4)[:dim]
+    mesh = I.UniformMesh(dim, n)
+    om = O.OracleMesh.uniform(mesh)
+    counts = np.random.default_rng(9).integers(0, 30, mesh.n_cells).astype(np.int32)
+    counts[3] = 0
+    seed, first = 123456789, 1000
+    st = O.seed_per_cell(om, counts, seed, first, n_prop=dim + 1)
+    N = int(counts.sum())
+    assert st.n == N
+    assert np.array_equal(st.id[:N], first + np.arange(N, dtype=np.uint32))
+    cell = np.repeat(np.arange(mesh.n_cells), counts)
+    assert np.array_equal(st.cell[:N], cell)
+    slot = np.arange(N) - np.repeat(np.cumsum(counts) - counts, counts)
+    for p in np.random.default_rng(10).choice(N, 60, replace=False):
+        want = [_u01(seed, _M64, int(cell[p]), int(slot[p]), a) for a in range(dim)]
+        assert np.array_equal(st.xr[:, p], want)
+    h = np.array([1.0 / k for k in n])
+    ijk = np.stack([(cell // int(np.prod(n[:a]))) % n[a] for a in range(dim)])
+    x = (ijk + st.xr[:, :N]) * h[:, None]
+    assert np.abs(st.x[:, :N] - x).max() <= 4e-16          # a few ulps: the map rounds in its own order
+    assert np.array_equal(st.prop[:dim, :N], st.x[:, :N])
+    assert np.array_equal(st.prop[dim, :N], st.x[0, :N])
+    xr = st.xr[:, :N]
+    assert xr.min() >= 0.0 and xr.max() < 1.0
+    sig = np.sqrt(1.0 / 12.0 / N)
+    assert np.abs(xr.mean(axis=1) - 0.5).max() < 5 * sig
+    # other seeds give other points; equal seeds equal points
+    st2 = O.seed_per_cell(om, counts, seed + 1, first, n_prop=0)
+    assert not np.array_equal(st2.xr[:, :N], xr)
+    st3 = O.seed_per_cell(om, counts, seed, 0, n_prop=0)
+    assert np.array_equal(st3.xr[:, :N], xr)
