@@ -104,14 +104,24 @@ typedef struct {
     int64_t live;         /* live particles in the current buffer */
     int64_t lost;         /* removed because a stage or end point left the domain (Sec. 2.4, option 3) */
     int64_t moved;        /* particles that changed cell in a step */
-    int64_t near_face;    /* particles within 1e-10 of a face in reference coordinates (or of the boundary) */
-    int64_t first_try;    /* movers found in the first neighbour searched (Sec. 2.4, search order) */
-    int64_t fallback;     /* locations that needed the global search */
+    int64_t near_face;    /* particles of a step whose end point lies within 1e-10 of a cell face in
+                             reference coordinates, or one of whose points up to the first one outside
+                             the domain lies within 1e-10 h of the domain boundary (inside or outside);
+                             lost particles included */
+    /* Location by the neighbour search of Sec. 2.4 (displaced and octree
+     * meshes; uniform meshes locate by the closed form and leave these 0).
+     * Every stage point and end point that is not in its hint cell starts one
+     * search; the first-try hit rate of the paper's search order is
+     * first_try / searches. */
+    int64_t first_try;    /* searches whose first candidate cell held the point */
+    int64_t fallback;     /* searches that ended in the global search */
     int64_t newton_fail;  /* inverse-map evaluations that did not converge */
     int64_t added;        /* population management: particles created (Sec. 2.5) */
     int64_t deleted;      /* population management: particles removed */
     int64_t steps;        /* time steps taken */
     int64_t particle_steps; /* sum over steps of the particles advanced */
+    int64_t searches;     /* points located by the neighbour search (not in their hint cell) */
+    int64_t searched;     /* candidate cells tried by those searches */
 } pic_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -195,6 +205,18 @@ PIC_API pic_status pic_current_buffer(pic_ctx *ctx, int32_t *which);
  * property j to coordinate j mod dim of x.  Replaces the current contents. */
 PIC_API pic_status pic_seed_reference(pic_ctx *ctx, const int32_t *counts, const double *xr, const uint32_t *ids,
                               int64_t n, int32_t prop_init, const void *prop_in);
+/* Reference-local generation with the library's counter hash (Sec. 2.2,
+ * remark on generating particles in the reference cell): counts[K]
+ * particles in cell K (device int32 [n_cells]), listed cell by cell; particle
+ * j of cell K at reference coordinates xr_a = u(seed, 2^64 - 1, K, j, a), u the
+ * SplitMix64 counter hash of pic_population (step word 2^64 - 1), location
+ * x = Phi_K(xr), id first_id + its position in the listing.  Properties as
+ * pic_seed_reference (prop_in device [n_prop][sum of counts] for
+ * PIC_PROP_GIVEN).  Replaces the current contents; PIC_ECAPACITY if the
+ * counts exceed the capacity, PIC_EINVAL for a negative count or ids beyond
+ * 2^32. */
+PIC_API pic_status pic_seed_per_cell(pic_ctx *ctx, const int32_t *counts, uint64_t seed, uint32_t first_id,
+                                     int32_t prop_init, const void *prop_in);
 /* Metropolis-Hastings generation (Sec. 2.2): counts[K] particles in cell K
  * (device int32 [n_cells]) drawn from the density rho (device double
  * [n_nodes], nodal values of its Q2 interpolant rho_h; hanging-node values of

@@ -30,7 +30,7 @@ EXPORTS = [
     "pic_mesh_uniform", "pic_mesh_displace", "pic_mesh_octree", "pic_mesh_info", "pic_q2_nodes",
     "pic_set_velocity", "pic_set_velocity_end", "pic_shift_velocity", "pic_set_field_time", "pic_field_time",
     "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
-    "pic_seed_reference", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
+    "pic_seed_reference", "pic_seed_per_cell", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
     "pic_interpolate", "pic_interpolate_points", "pic_seed_mh", "pic_transfer",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
@@ -49,7 +49,8 @@ class PicStore(C.Structure):
 
 class PicStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("live", "lost", "moved", "near_face", "first_try", "fallback",
-                                         "newton_fail", "added", "deleted", "steps", "particle_steps")]
+                                         "newton_fail", "added", "deleted", "steps", "particle_steps",
+                                         "searches", "searched")]
 
 
 class PicError(RuntimeError):
@@ -92,6 +93,7 @@ def load(path: str | None = None):
             "pic_current_buffer": (S, [P, P]),
             "pic_set_tile": (S, [P, I32]),
             "pic_seed_reference": (S, [P, P, P, P, I64, I32, P]),
+            "pic_seed_per_cell": (S, [P, P, C.c_uint64, C.c_uint32, I32, P]),
             "pic_seed_positions": (S, [P, P, P, I64, I32, P]),
             "pic_advance": (S, [P, D, I32, I32, I32]),
             "pic_set_property_odes": (S, [P, I32, I32, C.c_double, C.c_double]),

@@ -24,9 +24,11 @@ class ParticleFlow:
         self.n0 = int(xr.shape[1])
         self.dt, self.n_steps, self.scheme, self.ckpt = float(dt), int(n_steps), int(scheme), int(ckpt_every)
         self.ws = problem.adjoint_workspace(self.n_steps, self.ckpt)
+        self.runs = 0           # forward runs so far: the store and checkpoints hold the last one
 
     def run_forward(self, U, checkpoint=True):
         p = self.p
+        self.runs += 1
         p.set_velocity(U)
         p.seed_reference(self.counts, self.xr, self.ids)
         if checkpoint:
@@ -46,13 +48,23 @@ class _Advect(torch.autograd.Function):
         out, ids = flow.run_forward(U.detach(), checkpoint=True)
         ctx.flow = flow
         ctx.ids = ids
+        ctx.run = flow.runs
         ctx.shape = tuple(U.shape)
+        ctx.save_for_backward(U)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
         flow = ctx.flow
         p = flow.p
+        if flow.runs != ctx.run:
+            # another forward ran since: the store and the checkpoints belong to it, so this
+            # forward is run again from its own field before the reverse sweep
+            (U,) = ctx.saved_tensors
+            _, ids = flow.run_forward(U.detach(), checkpoint=True)
+            if not torch.equal(ids, ctx.ids):
+                raise RuntimeError("re-run of the forward gave a different particle set")
+            ctx.run = flow.runs
         cap = p.store.capacity
         dl = torch.zeros((p.dim, cap), dtype=torch.float64, device=p.device)
         n = ctx.ids.numel()

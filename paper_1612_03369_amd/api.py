@@ -200,6 +200,17 @@ class Problem:
         mode = L.PIC_PROP_INITIAL_POSITION if (init_position and prop is None) else L.PIC_PROP_GIVEN
         self._chk(self.lib.pic_seed_reference(self.h, _ptr(c), _ptr(x), _ptr(i), n, mode, _ptr(p)))
 
+    def seed_per_cell(self, counts, seed, first_id=0, prop=None, init_position=True):
+        """Reference-local generation with the library's counter hash (counts per cell)."""
+        torch = _torch()
+        dev = self.device
+        c = torch.as_tensor(np.ascontiguousarray(counts, np.int32)).to(dev)
+        p = None
+        if prop is not None:
+            p = torch.as_tensor(prop).to(dev).to(self.store.prop_dtype).contiguous()
+        mode = L.PIC_PROP_INITIAL_POSITION if (init_position and prop is None) else L.PIC_PROP_GIVEN
+        self._chk(self.lib.pic_seed_per_cell(self.h, _ptr(c), int(seed), int(first_id), mode, _ptr(p)))
+
     def seed_positions(self, x, ids, prop=None, init_position=True):
         torch = _torch()
         dev = self.device

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
                 if (st > 0) {
                     const double fct = (S == 4 && st == 3) ? 1.0 : 0.5;
                     for (int a = 0; a < D; ++a) y[a] = x[a] + fct * k[st - 1][a];
-                    locate_stage<D>(m, y, jk[st], ty[st], near);
+                    locate_stage<D>(m, y, jk[st], ty[st], near, true);
                 }
                 const int wq = wbase(jk[st]);
                 if (wq >= 0)
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_step(const ProblemDev *__rest
         ty[0][a] = xr_in[a * cap + s];
     }
     Ky[0] = cell_in[s];
-    LocStats ls = {0, 0, 0, 0};
+    LocStats ls = {0, 0, 0, 0, 0};
     constexpr int NS = S == 4 ? 4 : S;
     for (int st = 0; st < NS; ++st) {
         if (st > 0) {

@@ -202,7 +202,7 @@ __device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<ty
     } else if constexpr (S == 2) {
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
-        near |= near_boundary<D>(m, y);
+        near |= in & near_boundary<D>(m, y);
         in &= locate_uniform<D>(m, y, jk, ty);
         eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
 #pragma unroll
@@ -211,7 +211,7 @@ __device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<ty
         double k2[3], k3[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * k1[a];
-        near |= near_boundary<D>(m, y);
+        near |= in & near_boundary<D>(m, y);
         in &= locate_uniform<D>(m, y, jk, ty);
         eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
 #pragma unroll
@@ -219,7 +219,7 @@ __device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<ty
             k2[a] = dt * u[a];
             y[a] = x[a] + 0.5 * k2[a];
         }
-        near |= near_boundary<D>(m, y);
+        near |= in & near_boundary<D>(m, y);
         in &= locate_uniform<D>(m, y, jk, ty);
         eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
 #pragma unroll
@@ -227,14 +227,14 @@ __device__ __forceinline__ uint32_t advect_one_uniform(const MeshDev &m, gptr<ty
             k3[a] = dt * u[a];
             y[a] = x[a] + k3[a];
         }
-        near |= near_boundary<D>(m, y);
+        near |= in & near_boundary<D>(m, y);
         in &= locate_uniform<D>(m, y, jk, ty);
         eval_q2_ijk<D, T>(U, m.nnx, m.nny, jk, ty, u);
         const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + k1[a] * s6 + k2[a] * s3 + k3[a] * s3 + (dt * u[a]) * s6;
     }
-    near |= near_boundary<D>(m, xn);
+    near |= in & near_boundary<D>(m, xn);
     double tn[3];
     in &= locate_uniform<D>(m, xn, jk, tn);
     if (!in) return LOST;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
         for (int k = threadIdx.x; k < nt; k += BLOCK) s_cnt[k] = 0;
         __syncthreads();
         int st_lost = 0, st_moved = 0, st_near = 0;
-        LocStats ls = {0, 0, 0, 0};
+        LocStats ls = {0, 0, 0, 0, 0};
         for (int i = p0 + threadIdx.x; i < p1; i += BLOCK) {
             const int32_t K = cur.cell[i];
             double x[3], t[3];
@@ -397,6 +397,7 @@ __global__ __launch_bounds__(BLOCK) PIC_ADVECT_ATTR void k_advect(const ProblemD
             flush_stats(P.scr.stats, ST_FALLBACK, ls.fallback, nullptr);
             flush_stats(P.scr.stats, ST_NEWTON_FAIL, ls.newton_fail, nullptr);
             flush_stats(P.scr.stats, ST_SEARCHED, ls.searched, nullptr);
+            flush_stats(P.scr.stats, ST_SEARCHES, ls.searches, nullptr);
         }
         __syncthreads();
     }
@@ -442,7 +443,7 @@ k_advect_oct(const ProblemDev *__restrict__ probs,
                 eval_q2<3, T, MESH_OCTREE>(m, U, Kc, tc, uc);
         };
         int st_lost = 0, st_moved = 0, st_near = 0;
-        LocStats ls = {0, 0, 0, 0};
+        LocStats ls = {0, 0, 0, 0, 0};
         for (int i = p0 + threadIdx.x; i < p1; i += BLOCK) {
             const int32_t K = cur.cell[i];
             double x[3], t[3];
@@ -478,6 +479,7 @@ k_advect_oct(const ProblemDev *__restrict__ probs,
         flush_stats(P.scr.stats, ST_FALLBACK, ls.fallback, nullptr);
         flush_stats(P.scr.stats, ST_NEWTON_FAIL, ls.newton_fail, nullptr);
         flush_stats(P.scr.stats, ST_SEARCHED, ls.searched, nullptr);
+        flush_stats(P.scr.stats, ST_SEARCHES, ls.searches, nullptr);
         __syncthreads();
     }
 }
@@ -540,7 +542,7 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, 
     } else if constexpr (S == 2) {
 #pragma unroll
         for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * (dt * u[a]);
-        in &= locate_stage<D>(m, y, jk, ty, near);
+        in &= locate_stage<D>(m, y, jk, ty, near, in);
         ev(1, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = x[a] + dt * u[a];
@@ -555,7 +557,7 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, 
             xn[a] = x[a] + k[a] * s6;
             y[a] = x[a] + 0.5 * k[a];
         }
-        in &= locate_stage<D>(m, y, jk, ty, near);
+        in &= locate_stage<D>(m, y, jk, ty, near, in);
         ev(1, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -563,7 +565,7 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, 
             xn[a] = xn[a] + k[a] * s3;
             y[a] = x[a] + 0.5 * k[a];
         }
-        in &= locate_stage<D>(m, y, jk, ty, near);
+        in &= locate_stage<D>(m, y, jk, ty, near, in);
         ev(1, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -571,12 +573,12 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, 
             xn[a] = xn[a] + k[a] * s3;
             y[a] = x[a] + k[a];
         }
-        in &= locate_stage<D>(m, y, jk, ty, near);
+        in &= locate_stage<D>(m, y, jk, ty, near, in);
         ev(2, jk, ty, u);
 #pragma unroll
         for (int a = 0; a < D; ++a) xn[a] = xn[a] + (dt * u[a]) * s6;
     }
-    near |= near_boundary<D>(m, xn);
+    near |= in & near_boundary<D>(m, xn);
     double tn[3];
     in &= locate_uniform<D>(m, xn, jk, tn);
     if (!in) return LOST;
@@ -653,7 +655,7 @@ __device__ __forceinline__ uint32_t advect_one_blk_ode(const MeshDev &m, Eval &&
             for (int q = 0; q < NP; ++q) Ps[q] = Pp[q];
         } else {
             const double c = (S == 4 && s == 3) ? 1.0 : 0.5;
-            in &= locate_stage<D>(m, y, jk, ty, near);
+            in &= locate_stage<D>(m, y, jk, ty, near, in);
             ev(S == 4 && s == 3 ? 2 : 1, jk, ty, u);
             gr(S == 4 && s == 3 ? 2 : 1, jk, ty, G);
 #pragma unroll
@@ -690,7 +692,7 @@ __device__ __forceinline__ uint32_t advect_one_blk_ode(const MeshDev &m, Eval &&
         else if constexpr (S == 2) Pn[q] = Pp[q] + kP[1][q];
         else Pn[q] = Pp[q] + kP[0][q] * s6 + kP[1][q] * s3 + kP[2][q] * s3 + kP[3][q] * s6;
     }
-    near |= near_boundary<D>(m, xn);
+    near |= in & near_boundary<D>(m, xn);
     double tn[3];
     in &= locate_uniform<D>(m, xn, jk, tn);
     if (!in) return LOST;

@@ -622,15 +622,22 @@ pic_status load_field(pic_ctx *c, const void *U, int prec, void **d64, void **d3
     if (s) return s;
     HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
     unsigned grid = (unsigned)((nn + BLOCK - 1) / BLOCK);
-    if (d == 3)
-        hipLaunchKernelGGL(k_repack_field<3>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, flag);
-    else
-        hipLaunchKernelGGL(k_repack_field<2>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, flag);
+    // first a pass that only checks the values, so that a rejected field
+    // leaves the previous one in place
+    auto pass = [&](int *f) {
+        if (d == 3)
+            hipLaunchKernelGGL(k_repack_field<3>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, f);
+        else
+            hipLaunchKernelGGL(k_repack_field<2>, dim3(grid), dim3(BLOCK), 0, c->stream, U, prec == PIC_F32, nn, *d64, *d32, f);
+    };
+    pass(flag);
     int hflag = 0;
     HIPCHK(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     hipFree(flag);
     if (hflag) return fail(c, PIC_ENONFINITE, "velocity has NaN or infinite values");
+    pass(nullptr);
+    HIPCHK(c, hipGetLastError());
     if (c->mesh.kind == MESH_OCTREE) return resolve_hanging(c, *d64, *d32);
     return PIC_OK;
 }
@@ -809,18 +816,23 @@ extern "C" pic_status pic_current_buffer(pic_ctx *c, int32_t *which)
 // ===========================================================================
 namespace {
 template <int D>
-pic_status seed_ref_launch(pic_ctx *c, const double *xr, const uint32_t *ids, int64_t n, int pi, const void *pin)
+pic_status seed_ref_launch(pic_ctx *c, const double *xr, const uint32_t *ids, int64_t n, int pi, const void *pin,
+                           uint64_t seed, uint32_t first_id)
 {
     unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK / 64 - 1) / (BLOCK / 64));
     switch (c->mesh.kind) {
     case MESH_UNIFORM:
-        LAUNCH(c, "seed", (k_seed_reference<D, MESH_UNIFORM>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+        LAUNCH(c, "seed", (k_seed_reference<D, MESH_UNIFORM>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin, seed,
+               first_id);
         break;
     case MESH_DISPLACED:
-        LAUNCH(c, "seed", (k_seed_reference<D, MESH_DISPLACED>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+        LAUNCH(c, "seed", (k_seed_reference<D, MESH_DISPLACED>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin, seed,
+               first_id);
         break;
     default:
-        if constexpr (D == 3) LAUNCH(c, "seed", (k_seed_reference<D, MESH_OCTREE>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin);
+        if constexpr (D == 3)
+            LAUNCH(c, "seed", (k_seed_reference<D, MESH_OCTREE>), grid, BLOCK, c->d_prob, 0, xr, ids, n, pi, pin, seed,
+                   first_id);
     }
     return PIC_OK;
 }
@@ -843,15 +855,18 @@ pic_status seed_pos_launch(pic_ctx *c, const double *x, const uint32_t *ids, int
 }
 }  // namespace
 
-extern "C" pic_status pic_seed_reference(pic_ctx *c, const int32_t *counts, const double *xr, const uint32_t *ids, int64_t n,
-                                         int32_t prop_init, const void *prop_in)
+namespace {
+// Reference-local generation into the current buffer: counts per cell
+// (device), cell_start = their exclusive scan.  xr == NULL: reference points
+// from the counter hash with ids first_id + position (n = -1: the sum of the
+// counts); else xr / ids as given for n particles.
+pic_status seed_cells(pic_ctx *c, const int32_t *counts, const double *xr, const uint32_t *ids, int64_t n,
+                      int32_t prop_init, const void *prop_in, uint64_t seed, uint32_t first_id)
 {
     pic_status s = require_ready(c, false);
     if (s) return s;
-    if (!counts || (n > 0 && (!xr || !ids))) return fail(c, PIC_EINVAL, "null argument");
-    if (n < 0 || n > c->store.capacity) return fail(c, PIC_ECAPACITY, "n=%lld exceeds capacity %lld", (long long)n, (long long)c->store.capacity);
+    if (!counts || (xr && n > 0 && !ids)) return fail(c, PIC_EINVAL, "null argument");
     if (prop_init != PIC_PROP_GIVEN && prop_init != PIC_PROP_INITIAL_POSITION) return fail(c, PIC_EINVAL, "bad prop_init");
-    if (prop_init == PIC_PROP_GIVEN && c->store.n_prop > 0 && n > 0 && !prop_in) return fail(c, PIC_EINVAL, "null prop_in");
     hipSetDevice(c->device);
     // cell_start of the current buffer = exclusive scan of counts; check the total
     std::vector<int32_t> h(c->mesh.n_cells);
@@ -865,16 +880,36 @@ extern "C" pic_status pic_seed_reference(pic_ctx *c, const int32_t *counts, cons
         run += h[k];
     }
     cs[h.size()] = (int32_t)run;
+    if (!xr) n = run;
+    if (n < 0 || n > c->store.capacity) return fail(c, PIC_ECAPACITY, "n=%lld exceeds capacity %lld", (long long)n, (long long)c->store.capacity);
     if (run != n) return fail(c, PIC_EINVAL, "sum of counts %lld != n %lld", (long long)run, (long long)n);
+    if (!xr && (uint64_t)first_id + (uint64_t)n > 0x100000000ull) return fail(c, PIC_EINVAL, "ids beyond 2^32");
+    if (prop_init == PIC_PROP_GIVEN && c->store.n_prop > 0 && n > 0 && !prop_in) return fail(c, PIC_EINVAL, "null prop_in");
     int32_t cur = 0;
     if ((s = pic_current_buffer(c, &cur))) return s;
     HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur], cs.data(), sizeof(int32_t) * cs.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->scr.next_id, 0, 8 * (1 + STAT_STRIPES), c->stream));
-    s = c->mesh.dim == 2 ? seed_ref_launch<2>(c, xr, ids, n, prop_init, prop_in) : seed_ref_launch<3>(c, xr, ids, n, prop_init, prop_in);
+    s = c->mesh.dim == 2 ? seed_ref_launch<2>(c, xr, ids, n, prop_init, prop_in, seed, first_id)
+                         : seed_ref_launch<3>(c, xr, ids, n, prop_init, prop_in, seed, first_id);
     if (s) return s;
     LAUNCH(c, "seed", k_reduce_next_id, 1u, (unsigned)STAT_STRIPES, (const ProblemDev *)c->d_prob);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_seed_reference(pic_ctx *c, const int32_t *counts, const double *xr, const uint32_t *ids, int64_t n,
+                                         int32_t prop_init, const void *prop_in)
+{
+    if (c && n > 0 && !xr) return fail(c, PIC_EINVAL, "null argument");
+    static const double none = 0.0;     // marks "given" for an empty input (never read)
+    return seed_cells(c, counts, n > 0 ? xr : &none, ids, n, prop_init, prop_in, 0, 0);
+}
+
+extern "C" pic_status pic_seed_per_cell(pic_ctx *c, const int32_t *counts, uint64_t seed, uint32_t first_id,
+                                        int32_t prop_init, const void *prop_in)
+{
+    return seed_cells(c, counts, nullptr, nullptr, -1, prop_init, prop_in, seed, first_id);
 }
 
 extern "C" pic_status pic_seed_positions(pic_ctx *c, const double *x, const uint32_t *ids, int64_t n, int32_t prop_init,
@@ -1223,6 +1258,8 @@ extern "C" pic_status pic_stats_read(pic_ctx *c, pic_stats *out)
     out->deleted = (int64_t)st[ST_DELETED];
     out->steps = (int64_t)st[ST_STEPS];
     out->particle_steps = (int64_t)st[ST_PSTEPS];
+    out->searches = (int64_t)st[ST_SEARCHES];
+    out->searched = (int64_t)st[ST_SEARCHED];
     return PIC_OK;
 }
 

@@ -28,7 +28,7 @@ enum MeshKind : int { MESH_UNIFORM = 0, MESH_DISPLACED = 1, MESH_OCTREE = 2 };
 // Counter slots in the device statistics array.
 enum StatSlot : int {
     ST_LOST = 0, ST_MOVED, ST_NEAR, ST_FIRST_TRY, ST_FALLBACK, ST_NEWTON_FAIL, ST_ADDED, ST_DELETED,
-    ST_STEPS, ST_SEARCHED, ST_PSTEPS, ST_COUNT = 16
+    ST_STEPS, ST_SEARCHED, ST_PSTEPS, ST_SEARCHES, ST_COUNT = 16
 };
 // Counters are spread over STAT_STRIPES copies (one 128-byte line each),
 // picked by workgroup index, so that no address sees more than a sliver of
@@ -452,26 +452,32 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
 }
 
 // Stage-point location on a uniform mesh: cell and reference coordinates from
-// s = (y - lo)/h; inside = 0 <= s <= n per axis; near = within 1e-10 of the
-// domain boundary.  Reference coordinates s - i are accurate to a few ulps of
-// s, which only feeds the field evaluation; stored locations use
-// locate_uniform.
+// s = (y - lo)/h; inside = 0 <= s <= n per axis.  `live` says whether every
+// earlier point of the step was inside the domain: only then is the point
+// tested for the near-boundary band (|y - lo| or |y - hi| below 1e-10 h on
+// some axis, inside or outside), as a step that stops at its first point
+// outside the domain would test it.  Reference coordinates s - i are accurate
+// to a few ulps of s, which only feeds the field evaluation; stored locations
+// use locate_uniform.
 template <int D>
-__device__ __forceinline__ bool locate_stage(const MeshDev &m, const double *y, int ijk[3], double *t, bool &near)
+__device__ __forceinline__ bool locate_stage(const MeshDev &m, const double *y, int ijk[3], double *t, bool &near,
+                                             bool live)
 {
-    bool inside = true;
+    bool inside = true, nb = false;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double s = (y[a] - m.lo[a]) * m.inv_h[a];
+        const double d = y[a] - m.lo[a];
+        const double s = d * m.inv_h[a];
         const double n = (double)m.n[a];
         inside &= (s >= 0.0) & (s <= n);
-        near |= (s < NEAR_TOL) | (s > n - NEAR_TOL);
+        nb |= (fabs(d) < m.bnd_tol[a]) | (fabs(y[a] - m.hi[a]) < m.bnd_tol[a]);
         int i = (int)floor(s);
         i = i >= m.n[a] ? m.n[a] - 1 : (i < 0 ? 0 : i);
         t[a] = s - (double)i;
         ijk[a] = i;
     }
     if constexpr (D == 2) ijk[2] = 0;
+    near |= live & nb;
     return inside;
 }
 
@@ -678,8 +684,11 @@ template <int D> __device__ __forceinline__ bool near_boundary(const MeshDev &m,
 }
 
 // Location statistics gathered per thread.
+// first_try: searches whose first candidate held the point; fallback:
+// searches that ended in the global search; searched: candidate cells tried;
+// searches: points not in their hint cell (each starts one search).
 struct LocStats {
-    int first_try, fallback, newton_fail, searched;
+    int first_try, fallback, newton_fail, searched, searches;
 };
 
 // Global search of a displaced mesh: every cell whose bounding box (+1e-10)
@@ -812,6 +821,7 @@ __device__ __forceinline__ bool locate(const MeshDev &m, const double *y, int32_
             for (int a = 0; a < D; ++a) t[a] = tt[a];
             return true;
         }
+        ls.searches++;
         // Cells sharing the hint's vertex v closest to y, in descending order
         // of a.b with a = y - v and b = c_K' - v (ties: lower cell index
         // first), then the global search.  The order is walked without a

@@ -264,8 +264,8 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 // the others' so that the threads of a wave hit distinct banks).  Cells with
 // more (an unsorted input, a coarsened mesh) are sorted afterwards one at a
 // time by the whole workgroup: each arrival's rank among the cell's arrivals
-// (the positions are distinct) is its slot; cells beyond the LDS buffer
-// (very rare) by one thread in global memory.
+// (the positions are distinct) is its slot; beyond what LDS holds, the ranks
+// are counted over LDS-sized tiles (n^2 / 256 LDS reads per thread).
 constexpr int FIX_LDS = 32;
 __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                int n_items)
@@ -341,16 +341,30 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
                 __syncthreads();
                 for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = o[q];
                 __syncthreads();
-            } else if (threadIdx.x == 0) {
-                for (int q = 1; q < nn; ++q) {
-                    const int32_t x = a[q];
-                    int r = q - 1;
-                    while (r >= 0 && a[r] > x) {
-                        a[r + 1] = a[r];
-                        --r;
+            } else {
+                // more arrivals than LDS holds: the same ranks, counted over
+                // LDS-sized tiles of the cell's slots, with the sorted list
+                // built in the other buffer's key array at the same indices
+                // (unused until the next advect writes it) and copied back
+                auto t = (gptr_mut<int32_t>)((int32_t *)P.scr.key[1 - P.cur] + s_big_b[c]);
+                constexpr int TILE = FIX_LDS * BLOCK;
+                for (int q0 = 0; q0 < nn; q0 += BLOCK) {
+                    const int q = q0 + (int)threadIdx.x;
+                    const int32_t x = q < nn ? a[q] : 0;
+                    int r = 0;
+                    for (int j0 = 0; j0 < nn; j0 += TILE) {
+                        const int m = min(TILE, nn - j0);
+                        __syncthreads();
+                        for (int j = threadIdx.x; j < m; j += BLOCK) s_v[j] = a[j0 + j];
+                        __syncthreads();
+                        if (q < nn)
+                            for (int j = 0; j < m; ++j) r += s_v[j] < x;
                     }
-                    a[r + 1] = x;
+                    if (q < nn) t[r] = x;
                 }
+                __syncthreads();
+                for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = t[q];
+                __syncthreads();
             }
         }
         __syncthreads();
@@ -407,14 +421,42 @@ __global__ void k_flip(ProblemDev *probs, int n_probs, int count_step)
 }
 
 // ===========================================================================
+// counter-based random numbers: SplitMix64 (Steele, Lea, Flood 2014) chained
+// over the words of a counter (seed, step, cell, slot, axis) -> 53-bit
+// uniform in [0, 1)
+// ===========================================================================
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t step, uint64_t cell, uint64_t slot, uint64_t axis)
+{
+    uint64_t h = splitmix64(seed);
+    h = splitmix64(h ^ step);
+    h = splitmix64(h ^ cell);
+    h = splitmix64(h ^ slot);
+    h = splitmix64(h ^ axis);
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// step word of the reference-local generation stream (population steps use
+// their step number, Metropolis-Hastings 1 and 2)
+constexpr uint64_t SEED_STREAM = ~0ull;
+
+// ===========================================================================
 // generation (Sec. 2.2)
 // ===========================================================================
 // Reference-local generation: one wavefront per cell K writes the cell's
-// particles p in [cs[K], cs[K+1]) at x = Phi_K(xr).
+// particles p in [cs[K], cs[K+1]) at x = Phi_K(xr).  xr_in == NULL: particle
+// j of the cell takes xr_a = hash_u01(seed, SEED_STREAM, K, j, a) and id
+// first_id + p (ids is then unused).
 template <int D, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int prob, const double *__restrict__ xr_in,
                                                           const uint32_t *__restrict__ ids, int64_t n, int prop_init,
-                                                          const void *prop_in)
+                                                          const void *prop_in, uint64_t seed, uint32_t first_id)
 {
     const ProblemDev &P = probs[prob];
     const MeshDev &m = P.mesh;
@@ -427,21 +469,26 @@ __global__ __launch_bounds__(BLOCK) void k_seed_reference(ProblemDev *probs, int
     unsigned long long idmax = 0;
     for (int64_t p = b + lane; p < e && p < n; p += 64) {
         double t[3], x[3];
-        for (int a = 0; a < D; ++a) t[a] = xr_in[a * n + p];
+        if (xr_in) {
+            for (int a = 0; a < D; ++a) t[a] = xr_in[a * n + p];
+        } else {
+            for (int a = 0; a < D; ++a) t[a] = hash_u01(seed, SEED_STREAM, (uint64_t)K, (uint64_t)(p - b), (uint64_t)a);
+        }
         map_to_real<D, KIND>(m, K, t, x);
         for (int a = 0; a < D; ++a) {
             cur.x[a * cap + p] = x[a];
             cur.xr[a * cap + p] = t[a];
         }
         cur.cell[p] = (int32_t)K;
-        cur.id[p] = ids[p];
+        const uint32_t idp = xr_in ? ids[p] : first_id + (uint32_t)p;
+        cur.id[p] = idp;
         for (int j = 0; j < P.n_prop; ++j) {
             double v = prop_init == 1 ? x[j % D]
                                       : (P.prop_f64 ? ((const double *)prop_in)[j * n + p] : (double)((const float *)prop_in)[j * n + p]);
             if (P.prop_f64) ((double *)cur.prop)[j * cap + p] = v;
             else ((float *)cur.prop)[j * cap + p] = (float)v;
         }
-        idmax = idmax > (unsigned long long)ids[p] + 1ull ? idmax : (unsigned long long)ids[p] + 1ull;
+        idmax = idmax > (unsigned long long)idp + 1ull ? idmax : (unsigned long long)idp + 1ull;
     }
     if (idmax) atomicMax(&P.scr.next_id[1 + blockIdx.x % STAT_STRIPES], idmax);
 }
@@ -484,7 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_transfer_in(const ProblemDev *src_pro
     if (mine)
         for (int a = 0; a < D; ++a) x[a] = src.x[a * scap + p];
     int32_t K = -1;
-    LocStats ls = {0, 0, 0, 0};
+    LocStats ls = {0, 0, 0, 0, 0};
     bool ok = mine && in_box_domain<D>(m, x);
     if (ok) {
         if constexpr (KIND == MESH_UNIFORM) {
@@ -533,7 +580,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_positions(ProblemDev *probs, int
     if (mine)
         for (int a = 0; a < D; ++a) x[a] = x_in[a * n + p];
     int32_t K = -1;
-    LocStats ls = {0, 0, 0, 0};
+    LocStats ls = {0, 0, 0, 0, 0};
     bool ok = mine && in_box_domain<D>(m, x);
     if (ok) {
         if constexpr (KIND == MESH_UNIFORM) {
@@ -823,23 +870,6 @@ __global__ __launch_bounds__(BLOCK) void k_interp_lls(const ProblemDev *__restri
 // ===========================================================================
 // population management (Sec. 2.5; properties of new particles Sec. 2.6)
 // ===========================================================================
-__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
-{
-    z += 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t step, uint64_t cell, uint64_t slot, uint64_t axis)
-{
-    uint64_t h = splitmix64(seed);
-    h = splitmix64(h ^ step);
-    h = splitmix64(h ^ cell);
-    h = splitmix64(h ^ slot);
-    h = splitmix64(h ^ axis);
-    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
-}
-
 // Scalar density repacked into the field layout (value in the first component).
 template <int D>
 __global__ void k_pack_density(const double *__restrict__ rho, int64_t nn, typename NodeVec<D, double>::type *R,
@@ -1039,9 +1069,12 @@ __global__ void k_repack_field(const void *U, int src_f32, int64_t nn, void *u64
     if (g >= nn) return;
     double v[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) v[a] = src_f32 ? (double)((const float *)U)[a * nn + g] : ((const double *)U)[a * nn + g];
-    bool bad = false;
-    for (int a = 0; a < D; ++a) bad |= !isfinite(v[a]);
-    if (bad) atomicOr(flag, 1);
+    if (flag) {                 // check pass: nothing is written but the flag
+        bool bad = false;
+        for (int a = 0; a < D; ++a) bad |= !isfinite(v[a]);
+        if (bad) atomicOr(flag, 1);
+        return;
+    }
     if constexpr (D == 3) {
         ((double4 *)u64)[g] = make_double4(v[0], v[1], v[2], 0.0);
         ((float4 *)u32)[g] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);

@@ -146,3 +146,86 @@ def test_fused_steps_carry_any_number_of_properties(L, n_prop, dtype):
         pos = order[np.searchsorted(ids[order], g["id"])]
         assert np.array_equal(g["prop"], prop[:, pos])
     _say(f"  {g['id'].size} particles after {steps} fused steps")
+
+
+@pytest.mark.parametrize("kind", ["uniform", "octree"])
+def test_rejected_field_keeps_the_previous_one(L, kind):
+    """A field with a NaN or an infinity is rejected (PIC_ENONFINITE) before anything is
+    overwritten: the previous field, hanging nodes resolved, stays in use, in both precisions."""
+    _say(f"case: rejected non-finite field, {kind}")
+    from paper_1612_03369_amd._lib import PicError
+    from paper_1612_03369_amd.api import Problem
+    from helpers import oracle_run_tracking
+    p = Problem(0)
+    if kind == "octree":
+        lv, an = I.octree_shell_leaves(base_level=1, max_level=4, r_in=0.0, r_out=0.2, width=1.0,
+                                       centre=(0.3, 0.35, 0.4))
+        lv, an = I.balance_octree(lv, an, 4)
+        p.mesh_octree(lv, an, 4)
+        om = O.OracleMesh.octree(lv, an, 4)
+        nodes = om.q2_node_coords()
+        dim = 3
+    else:
+        mesh = I.UniformMesh(3, (6, 5, 4))
+        p.mesh_uniform(3, mesh.n)
+        om = O.OracleMesh.uniform(mesh)
+        nodes = I.uniform_q2_nodes(mesh)
+        dim = 3
+    Uraw = I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=88).velocity, nodes))
+    U = om.resolve_hanging(Uraw) if kind == "octree" else Uraw
+    p.set_velocity(Uraw)
+    bad = Uraw.copy()
+    bad[1, 7] = np.nan
+    bad[2, -1] = np.inf
+    for b in (bad, bad.astype(np.float32)):
+        with pytest.raises(PicError) as e:
+            p.set_velocity(b)
+        assert e.value.status == L.PIC_ENONFINITE
+    counts = np.full(om.n_cells, 4, np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=89)
+    p.allocate(xr.shape[1], n_prop=0)
+    for prec in (L.PIC_F64, L.PIC_F32):
+        p.seed_reference(counts, xr, ids)
+        p.advance(0.02, 5, L.PIC_RK2, prec)
+        g = p.numpy()
+        st = O.seed(om, counts, xr, ids, 0)
+        near, _ = oracle_run_tracking(om, U, 0.02, 2, 5, st)
+        o = st.view()
+        common, gi, oi = np.intersect1d(g["id"], o["id"], return_indices=True)
+        assert len(common) > 0.9 * xr.shape[1]
+        err = np.abs(g["x"][:, gi] - o["x"][:, oi]).max()
+        assert err <= (1e-12 if prec == L.PIC_F64 else 1e-6), err
+    p.close()
+
+
+def test_crowded_cells_beyond_the_lds_sort(L):
+    """Prescribed locations with thousands of particles in one cell (more than the LDS rank sort
+    holds: 5,000 and 9,000 arrivals, one and two LDS tiles): sorted by (cell, input order)."""
+    _say("case: 5,000 and 9,000 prescribed points in one cell each")
+    from paper_1612_03369_amd.api import Problem
+    mesh = I.UniformMesh(3, (4, 4, 4))
+    rng = np.random.default_rng(90)
+    n = 20000
+    x = rng.uniform(0.0, 1.0, size=(3, n))
+    x[:, 1000:6000] = rng.uniform(0.26, 0.49, size=(3, 5000))      # cell (1, 1, 1)
+    x[:, 8000:17000] = rng.uniform(0.76, 0.99, size=(3, 9000))     # cell (3, 3, 3)
+    perm = rng.permutation(n)
+    x = np.ascontiguousarray(x[:, perm])
+    ids = np.arange(n, dtype=np.uint32)
+    p = Problem(0)
+    p.mesh_uniform(3, mesh.n)
+    p.set_velocity(np.zeros((3, mesh.n_nodes)))
+    p.allocate(n, n_prop=1)
+    p.seed_positions(x, ids)
+    g = p.numpy()
+    om = O.OracleMesh.uniform(mesh)
+    cell = np.array([om.locate(x[:, i])[0] for i in range(n)])
+    exp = np.lexsort((np.arange(n), cell))
+    assert np.array_equal(g["id"], ids[exp])
+    assert np.array_equal(g["cell"], cell[exp])
+    big = np.bincount(cell, minlength=64)
+    assert big.max() >= 9000 and np.sort(big)[-2] >= 5000
+    # and a step of zero velocity keeps them (stayers in order)
+    p.advance(0.01, 2, L.PIC_RK4, L.PIC_F64)
+    assert np.array_equal(p.numpy()["id"], ids[exp])
+    p.close()

@@ -1,0 +1,242 @@
+"""Parity at the sizes and step counts the workloads are defined with, where the other GPU tests use
+smaller cases:
+
+* the timed configuration (64^3, 5,242,880 particles, RK4, FP32 evaluation, fused steps) at the
+  benchmark's 20 steps and the workload's 50, against the FP64 oracle with the gate
+  p99 |dx| <= 1e-6 and max |dx| <= 1e-5, cells re-checked by the oracle's location of the GPU's own
+  positions;
+* the adjoint workload in full (32^3, 1,048,576 particles, RK4 x 50, checkpoints every 10): the
+  GPU gradient against the oracle's per-particle reverse sweep (1e-10 relative) and central
+  differences along 32 random directions (1e-6 relative at eps = 1e-8), the loss taken over 1
+  particle in 97;
+* the batch of real batched-workload problems (2D and 3D, RK2 and RK4) against the oracle on
+  sampled ids.
+
+The oracle follows sampled particles only: particles move independently, and a stable sort
+restricted to a subset keeps the subset's order.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1612_03369_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1612_03369_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _sample_store(om, cfg, every, n_prop):
+    counts = np.asarray(cfg["counts"], np.int64)
+    cell_of = np.repeat(np.arange(counts.size), counts)
+    sel = np.nonzero(cfg["ids"] % every == 0)[0]
+    cs = np.bincount(cell_of[sel], minlength=counts.size).astype(np.int32)
+    return O.seed(om, cs, cfg["xr"][:, sel], cfg["ids"][sel], n_prop), cfg["ids"][sel]
+
+
+def _by_id(store, ids):
+    order = np.argsort(store["id"])
+    pos = order[np.searchsorted(store["id"][order], ids)]
+    assert np.array_equal(store["id"][pos], ids)
+    return pos
+
+
+# ----------------------------------------------------------------------------
+# the timed configuration, FP32 evaluation
+# ----------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_uniform64_fp32_gate_at_20_and_50_steps(L):
+    from paper_1612_03369_amd.api import Problem
+    cfg = I.config2()
+    _say("case: 64^3 RK4 FP32 evaluation, fused steps, 20 then 50 steps, sampled ids vs FP64 oracle")
+    p = Problem(0)
+    p.mesh_uniform(3, cfg["mesh"].n)
+    p.set_velocity(cfg["U"])
+    p.allocate(cfg["xr"].shape[1], n_prop=3, prop_dtype="float32")
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+    om = O.OracleMesh.uniform(cfg["mesh"])
+    st, sel = _sample_store(om, cfg, 89, 3)
+    done = 0
+    for upto in (20, 50):
+        p.advance(cfg["dt"], upto - done, L.PIC_RK4, L.PIC_F32)
+        O.run(om, cfg["U"], cfg["dt"], 4, upto - done, st)
+        done = upto
+        g = p.numpy()
+        o = st.view()
+        gmask = np.isin(g["id"], sel)
+        live_g = set(g["id"][gmask].tolist())
+        live_o = set(o["id"].tolist())
+        one_side = live_g ^ live_o
+        common = np.array(sorted(live_g & live_o), dtype=np.uint32)
+        gp, op = _by_id(g, common), _by_id(o, common)
+        dx = np.abs(g["x"][:, gp] - o["x"][:, op]).max(axis=0)
+        p99, mx = float(np.quantile(dx, 0.99)), float(dx.max())
+        # the cell of every GPU particle is where the oracle locates the GPU's own position
+        xs = g["x"][:, gp]
+        ks = np.array([om.locate(xs[:, k])[0] for k in range(xs.shape[1])])
+        assert np.array_equal(ks, g["cell"][gp])
+        # the sampled particles keep the oracle's relative order wherever both agree on the cell
+        same = g["cell"][gp] == o["cell"][op]
+        _say(f"  {upto} steps: {common.size} compared, p99 |dx| {p99:.2e}, max {mx:.2e}, "
+             f"cells differ {int((~same).sum())}, live on one side only {len(one_side)}")
+        assert p99 <= 1e-6 and mx <= 1e-5
+        assert len(one_side) <= max(3, common.size // 1000)
+        assert (~same).sum() <= max(3, common.size // 1000)
+    p.close()
+
+
+# ----------------------------------------------------------------------------
+# the adjoint workload in full
+# ----------------------------------------------------------------------------
+@pytest.mark.timeout(1200)
+def test_adjoint_full_size_oracle_and_central_differences(L):
+    import torch
+    from paper_1612_03369_amd.adjoint import ParticleFlow, advect
+    from paper_1612_03369_amd.api import Problem
+    cfg = I.config5()
+    n0 = cfg["xr"].shape[1]
+    dt, steps, every = cfg["dt"], cfg["steps"], 97
+    _say(f"case: adjoint 32^3, {n0} particles, RK4 x {steps}, checkpoints every {cfg['ckpt_every']}")
+    om = O.OracleMesh.uniform(cfg["mesh"])
+    # targets: the oracle's forward run of U + 0.1 U' plus noise, on the sampled particles
+    tg_st, sel = _sample_store(om, cfg, every, 0)
+    O.run(om, cfg["U"] + 0.1 * cfg["U_pert"], dt, 4, steps, tg_st)
+    base_st, _ = _sample_store(om, cfg, every, 0)
+    v0 = base_st.view()
+    O.run(om, cfg["U"], dt, 4, steps, base_st)
+    noise = I.target_noise(n0, 3, seed=cfg["noise_seed"], sigma=cfg["noise_sigma"])
+    tgt = np.zeros((3, n0))
+    t = tg_st.view()
+    tgt[:, t["id"]] = t["x"] + noise[:, t["id"]]
+    b = base_st.view()
+    mask = np.zeros(n0, bool)
+    mask[np.intersect1d(t["id"], b["id"])] = True
+    nv = int(mask.sum())
+    assert nv > 0.9 * sel.size
+    # oracle gradient: per-particle reverse sweep from the initial state of the sampled particles
+    Lo, dUo, _ = O.adjoint(om, cfg["U"], dt, 4, steps, v0["x"], v0["cell"], v0["xr"],
+                           np.ascontiguousarray(tgt[:, v0["id"]]), mask[v0["id"]].astype(np.uint8))
+    # GPU
+    p = Problem(0)
+    p.mesh_uniform(3, cfg["mesh"].n)
+    p.set_velocity(cfg["U"])
+    p.allocate(n0, n_prop=0)
+    flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, 4, cfg["ckpt_every"])
+    tgt_t = torch.tensor(tgt, device=p.device)
+    mask_t = torch.tensor(mask, device=p.device)
+
+    def loss_of(U):
+        xT = advect(U, flow)
+        assert not bool(torch.isnan(xT[:, mask_t]).any()), "a loss particle was lost on the GPU only"
+        return ((xT - tgt_t)[:, mask_t] ** 2).sum() / nv
+
+    U = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device, requires_grad=True)
+    lg = loss_of(U)
+    lg.backward()
+    lg = lg.detach()
+    g = U.grad.detach()
+    gn = g.cpu().numpy()
+    rel = np.abs(gn - dUo).max() / np.abs(dUo).max()
+    _say(f"  loss {float(lg):.6e} (oracle {Lo:.6e}), gradient rel err vs oracle {rel:.2e}")
+    assert abs(float(lg) - Lo) <= 1e-12 * abs(Lo)
+    assert rel <= 1e-10
+    # Central differences along 32 random directions.  L(U + s v) is piecewise smooth: where a stage
+    # point crosses a cell face as s changes, grad u_h jumps, so L is only C^1 there and a central
+    # difference over [-eps, eps] errs by O(eps) times the jump for every crossing inside it.  With
+    # |v|_inf = 1 on every node, eps = 1e-6 moves points by ~1e-6 and hundreds of the ~2e6 stage
+    # points cross a face; eps = 1e-8 leaves a few.  The difference of the two losses is summed as
+    # sum (x+ - x-) . (x+ + x- - 2 x*) so that it does not cancel at small eps.
+    V = I.fd_directions(32, g.numel(), seed=cfg["fd_seed"])
+    U0 = U.detach()
+
+    def x_of(Uv):
+        with torch.no_grad():
+            xT = advect(Uv, flow)[:, mask_t]
+        assert not bool(torch.isnan(xT).any())
+        return xT
+
+    tm = tgt_t[:, mask_t]
+    worst = {1e-6: 0.0, 1e-8: 0.0}
+    for k in range(V.shape[0]):
+        d = torch.tensor(V[k].reshape(g.shape), device=p.device)
+        an = float((g * d).sum())
+        for eps in worst:
+            xp, xm = x_of(U0 + eps * d), x_of(U0 - eps * d)
+            fd = float(((xp - xm) * (xp + xm - 2.0 * tm)).sum()) / nv / (2.0 * eps)
+            worst[eps] = max(worst[eps], abs(fd - an) / abs(an))
+        assert worst[1e-8] <= 1e-6, (k, worst)
+    _say(f"  32 central differences: worst rel gap {worst[1e-6]:.2e} at eps 1e-6, {worst[1e-8]:.2e} at eps 1e-8")
+    assert worst[1e-6] <= 1e-4
+    p.close()
+
+
+# ----------------------------------------------------------------------------
+# batched problems against the oracle
+# ----------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_batch_of_workload_problems_matches_oracle(L):
+    from paper_1612_03369_amd.api import Batch, Problem
+    cfgs = I.config4()
+    # two problems of every (dimension, scheme) pair, the smallest ones
+    pick = []
+    for dim in (2, 3):
+        for scheme in (2, 4):
+            cand = sorted((c["xr"].shape[1], q) for q, c in enumerate(cfgs)
+                          if c["mesh"].dim == dim and c["scheme"] == scheme)
+            pick += [q for _, q in cand[:2]]
+    sel_cfgs = [cfgs[q] for q in pick]
+    _say(f"case: batch of workload problems {pick} ({sum(c['xr'].shape[1] for c in sel_cfgs)} particles) "
+         f"vs the oracle, 20 steps")
+    probs = []
+    for c in sel_cfgs:
+        m = c["mesh"]
+        p = Problem(0)
+        p.mesh_uniform(m.dim, m.n[: m.dim])
+        p.set_velocity(c["U"])
+        p.allocate(c["xr"].shape[1], n_prop=1, prop_dtype="float64")
+        p.seed_reference(c["counts"], c["xr"], c["ids"])
+        probs.append(p)
+    b = Batch(probs)
+    b.advance([c["dt"] for c in sel_cfgs], [c["scheme"] for c in sel_cfgs], sel_cfgs[0]["steps"])
+    for q, c, p in zip(pick, sel_cfgs, probs):
+        g = p.numpy()
+        om = O.OracleMesh.uniform(c["mesh"])
+        st, sel = _sample_store(om, c, 53, 1)
+        from helpers import oracle_run_tracking
+        near, _ = oracle_run_tracking(om, c["U"], c["dt"], c["scheme"], c["steps"], st)
+        o = st.view()
+        gmask = np.isin(g["id"], sel)
+        live_g, live_o = set(g["id"][gmask].tolist()), set(o["id"].tolist())
+        assert not ((live_g ^ live_o) - near)
+        common = np.array(sorted(live_g & live_o), dtype=np.uint32)
+        gp, op = _by_id(g, common), _by_id(o, common)
+        err = (np.abs(g["x"][:, gp] - o["x"][:, op]).max(axis=0) /
+               np.maximum(1.0, np.abs(o["x"][:, op]).max(axis=0))).max()
+        assert err <= 1e-12, (q, err)
+        nm = np.isin(common.astype(np.int64), np.array(sorted(near), dtype=np.int64))
+        assert np.all((g["cell"][gp] == o["cell"][op]) | nm)
+        far = np.array(sorted(near), dtype=np.int64)
+        kg = gmask & ~np.isin(g["id"].astype(np.int64), far)
+        ko = ~np.isin(o["id"].astype(np.int64), far)
+        assert np.array_equal(g["id"][kg], o["id"][ko]), f"problem {q}: order of sampled particles"
+        assert p.stats()["steps"] == c["steps"]
+        _say(f"  problem {q}: {c['mesh'].dim}D n={c['mesh'].n[0]} rk{c['scheme']}, {common.size} sampled, "
+             f"max rel err {err:.2e}")
+    b.close()
+    for p in probs:
+        p.close()

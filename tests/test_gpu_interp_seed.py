@@ -185,3 +185,75 @@ def test_interpolation_and_generation_argument_checks(L):
     with pytest.raises(PicError):
         p.seed_mh(counts, rho, 2, 1, first_id=2 ** 32 - 10)     # ids would overflow
     p.close()
+
+
+# ----------------------------------------------------------------------------
+# reference-local generation with the library's counter hash (Sec. 2.2)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,dim", [("uniform", 2), ("uniform", 3), ("displaced", 3), ("octree", 3)])
+def test_seed_per_cell_matches_oracle(L, kind, dim):
+    """pic_seed_per_cell: reference coordinates, ids and cells bit-identical to the oracle's
+    counter-hash generation; locations Phi_K(xhat) within a few ulps; properties = locations."""
+    _say(f"case: seed per cell, {kind} {dim}D")
+    from paper_1612_03369_amd.api import Problem
+    p = Problem(0)
+    if kind == "octree":
+        lv, an = I.octree_shell_leaves(base_level=1, max_level=4, r_in=0.0, r_out=0.2, width=1.0,
+                                       centre=(0.3, 0.35, 0.4))
+        lv, an = I.balance_octree(lv, an, 4)
+        p.mesh_octree(lv, an, 4)
+        om = O.OracleMesh.octree(lv, an, 4)
+    else:
+        mesh = I.UniformMesh(dim, (9, 7, 6)[:dim])
+        p.mesh_uniform(dim, mesh.n[:dim])
+        om = O.OracleMesh.uniform(mesh)
+        if kind == "displaced":
+            vert = I.displaced_vertices(mesh, 0.2, seed=77)
+            p.mesh_displace(vert)
+            om = O.OracleMesh.displaced(mesh, vert)
+    nc = om.n_cells
+    counts = np.random.default_rng(78).integers(0, 25, nc).astype(np.int32)
+    counts[::11] = 0
+    n = int(counts.sum())
+    p.set_velocity(np.zeros((dim, p.n_nodes)))
+    p.allocate(30 * nc, n_prop=dim + 1, prop_dtype="float64")
+    p.seed_per_cell(counts, seed=2024, first_id=17)
+    g = p.numpy()
+    st = O.seed_per_cell(om, counts, 2024, 17, dim + 1)
+    o = st.view()
+    assert g["n"] == n == st.n
+    assert np.array_equal(g["id"], o["id"]) and np.array_equal(g["cell"], o["cell"])
+    assert np.array_equal(g["xr"], o["xr"])
+    assert np.array_equal(g["cell_start"], st.cell_start)
+    err = (np.abs(g["x"] - o["x"]) / np.maximum(1.0, np.abs(o["x"]))).max()
+    assert err <= 1e-15, err
+    assert np.abs(g["prop"] - o["prop"]).max() <= 1e-15
+    # the next id continues after the generated ones: population adds ids from there
+    p.population(max(1, int(counts.max())), 1000, 5, 0)
+    assert p.numpy()["id"].max() >= 17 + n
+    _say(f"  {n} particles identical in reference coordinates, ids and cells; location err {err:.1e}")
+    p.close()
+
+
+def test_seed_per_cell_argument_checks(L):
+    _say("case: seed per cell argument checks")
+    from paper_1612_03369_amd._lib import PicError
+    from paper_1612_03369_amd.api import Problem
+    p = Problem(0)
+    p.mesh_uniform(2, (4, 4))
+    p.set_velocity(np.zeros((2, p.n_nodes)))
+    p.allocate(50, n_prop=0)
+    with pytest.raises(PicError) as e:
+        p.seed_per_cell(np.full(16, 4, np.int32), seed=1)           # 64 > capacity 50
+    assert e.value.status == L.PIC_ECAPACITY
+    bad = np.full(16, 1, np.int32)
+    bad[3] = -1
+    with pytest.raises(PicError) as e:
+        p.seed_per_cell(bad, seed=1)
+    assert e.value.status == L.PIC_EINVAL
+    with pytest.raises(PicError) as e:
+        p.seed_per_cell(np.full(16, 1, np.int32), seed=1, first_id=0xFFFFFFF8)
+    assert e.value.status == L.PIC_EINVAL
+    p.seed_per_cell(np.zeros(16, np.int32), seed=1)
+    assert p.numpy()["n"] == 0
+    p.close()

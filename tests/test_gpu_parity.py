@@ -50,15 +50,22 @@ def test_config1_rotation_rk2_full(L):
     _say(f"  live {g['n']} (oracle {st.n}), lost {st_g['lost']} (oracle {lost}), max err {err:.2e}, near {nn}")
     assert st_g["lost"] + g["n"] == cfg["xr"].shape[1]
     assert st_g["steps"] == cfg["steps"]
-    if not near:
-        assert st_g["lost"] == lost
-        oavg, ocnt = O.cell_average(om.n_cells, st)
-        c = cnt.cpu().numpy()
-        assert np.array_equal(c, ocnt)
-        a = avg.cpu().numpy()[:, 0]
-        ok = ocnt > 0
-        assert np.all(np.isnan(a[~ok]))
-        assert np.allclose(a[ok], oavg[ok, 0], rtol=1e-13, atol=1e-15)
+    # lost counts differ only through particles the oracle saw near a face (the live sets were
+    # compared above); cell counts and averages are compared on every cell that holds no such
+    # particle on either side
+    assert abs(st_g["lost"] - lost) <= len(near)
+    oavg, ocnt = O.cell_average(om.n_cells, st)
+    nid = np.array(sorted(near), dtype=np.int64)
+    touched = np.zeros(om.n_cells, bool)
+    touched[g["cell"][np.isin(g["id"], nid)]] = True
+    touched[o["cell"][np.isin(o["id"], nid)]] = True
+    c = cnt.cpu().numpy()
+    assert np.array_equal(c[~touched], ocnt[~touched])
+    a = avg.cpu().numpy()[:, 0]
+    ok = (ocnt > 0) & ~touched
+    assert np.all(np.isnan(a[(ocnt == 0) & ~touched]))
+    assert np.allclose(a[ok], oavg[ok, 0], rtol=1e-13, atol=1e-15)
+    assert (~touched).sum() > 0.9 * om.n_cells
     p.close()
 
 

@@ -258,6 +258,42 @@ def test_adjoint_central_differences(L):
     p.close()
 
 
+def test_adjoint_backward_after_a_later_forward(L):
+    """Two forwards, then the backward of the first: the gradient is the first forward's (the flow
+    re-runs it from its own field), equal to a lone forward + backward up to the order of the FP64
+    atomic sums."""
+    _say("case: adjoint, backward after a later forward")
+    import torch
+    from paper_1612_03369_amd.adjoint import ParticleFlow, advect
+    cfg, dt, steps, scheme, ckpt = _adjoint_case(L, n=5, ppc=4, steps=9, ckpt=3, seed=321)
+    p = gpu_problem(cfg)
+    flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, scheme, ckpt)
+    U0 = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device)
+    U2 = torch.tensor(I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=322, tangential=True).velocity,
+                                                       I.uniform_q2_nodes(cfg["mesh"]))), device=p.device)
+    tgt = torch.zeros((3, cfg["xr"].shape[1]), dtype=torch.float64, device=p.device) + 0.5
+
+    def loss(xT):
+        m = ~torch.isnan(xT[0])
+        return ((xT - tgt)[:, m] ** 2).sum()
+
+    Ua = U0.clone().requires_grad_(True)
+    loss(advect(Ua, flow)).backward()
+    ref = Ua.grad.clone()
+    Ub = U0.clone().requires_grad_(True)
+    lb = loss(advect(Ub, flow))
+    Uc = U2.clone().requires_grad_(True)
+    lc = loss(advect(Uc, flow))
+    lb.backward()
+    assert torch.allclose(Ub.grad, ref, rtol=0, atol=1e-12 * float(ref.abs().max()))
+    lc.backward()
+    Ud = U2.clone().requires_grad_(True)
+    loss(advect(Ud, flow)).backward()
+    assert torch.allclose(Uc.grad, Ud.grad, rtol=0, atol=1e-12 * float(Ud.grad.abs().max()))
+    assert float((Uc.grad - ref).abs().max()) > 1e-6 * float(ref.abs().max())
+    p.close()
+
+
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("dim", [2, 3])
 def test_displaced_mesh_newton_and_neighbour_search(L, dim):
