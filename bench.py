@@ -650,29 +650,55 @@ def bench_interp(args):
     return r
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args):
-    """FP64 oracle on the host cores: the first steps of the same workload."""
+    """FP64 oracle on the host cores: a bounded sample of the same workload (the whole 64^3 store, its
+    first steps: one single-threaded, --cpu-steps on all the cores the process may use), median of 3
+    runs each (the paper averages 3 runs)."""
+    import statistics
+
     from oracle import oracle as O
     from paper_1612_03369_amd import inputs as I
 
     cfg = I.config2(eval_f32=True)
     om = O.OracleMesh.uniform(cfg["mesh"])
-    st = O.seed(om, cfg["counts"], cfg["xr"], cfg["ids"], 3)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    s = O.Stats()
-    t = time.perf_counter()
-    steps = 0
-    psteps = 0
-    while steps < args.cpu_steps:
-        psteps += st.n
-        O.step(om, cfg["U"], cfg["dt"], 4, st, s)
-        steps += 1
-        if time.perf_counter() - t > 25.0:
-            break
-    el = time.perf_counter() - t
-    log(f"[bench] cpu oracle: {steps} steps, {psteps} particle-steps in {el:.1f} s on {threads} threads")
-    return {"value": psteps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {steps} steps of the full workload ({cfg['xr'].shape[1]} particles), FP64 evaluation"}
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp_env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    all_threads = min(avail, omp_env) if omp_env else avail
+
+    def one_run(threads, steps):
+        used = O.set_threads(threads)
+        st = O.seed(om, cfg["counts"], cfg["xr"], cfg["ids"], 3)
+        s = O.Stats()
+        psteps = 0
+        t = time.perf_counter()
+        for _ in range(steps):
+            psteps += st.n
+            O.step(om, cfg["U"], cfg["dt"], 4, st, s)
+        return psteps / (time.perf_counter() - t), used
+
+    out = {}
+    for label, threads, steps in (("single", 1, 1), ("all", all_threads, args.cpu_steps)):
+        runs = [one_run(threads, steps) for _ in range(3)]
+        out[label] = (statistics.median(r[0] for r in runs), runs[0][1], steps)
+    O.set_threads(all_threads)
+    log(f"[bench] cpu oracle: single thread {out['single'][0]:.3e} p-s/s, {out['all'][1]} threads "
+        f"{out['all'][0]:.3e} p-s/s ({_cpu_model()}, {avail} cores available)")
+    return {"value": out["all"][0], "unit": "particle-steps/s", "cores": out["all"][1], "kind": "oracle",
+            "sample": f"the 64^3 RK4 store ({cfg['xr'].shape[1]} particles): first {out['all'][2]} steps on all "
+                      f"cores, first {out['single'][2]} single-threaded, FP64 evaluation, median of 3 runs each",
+            "single_thread_value": out["single"][0], "cpu_model": _cpu_model(), "nproc": avail,
+            "os_cpu_count": os.cpu_count()}
 
 
 def main():
@@ -683,7 +709,7 @@ def main():
     ap.add_argument("--extras", default="adjoint,batch,octree,odes,time_field,interp",
                     help="comma list: adjoint,batch,octree,odes,time_field,interp ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="print the counter summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("RUN_DIR", "TITLE", "COMMAND"),

@@ -101,6 +101,8 @@ def lib():
             L.orc_adjoint.restype = C.c_double
             L.orc_adjoint.argtypes = [P, P, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_int64,
                                       P, P, P, P, P, P, P]
+            L.orc_set_threads.restype = C.c_int
+            L.orc_set_threads.argtypes = [C.c_int]
             L.orc_seed_per_cell.restype = C.c_int
             L.orc_seed_per_cell.argtypes = [P, P, C.c_uint64, C.c_uint32, C.c_int, P]
             L.orc_octree_fine_table.restype = C.c_int
@@ -544,6 +546,11 @@ def adjoint(mesh: OracleMesh, U, dt, scheme, n_steps, x0, K0, xr0, target, mask)
     L = lib().orc_adjoint(C.byref(mesh.c), _p(U), U.shape[1], float(dt), int(scheme), int(n_steps),
                           x0.shape[1], _p(x0), _p(K0), _p(xr0), _p(target), _p(mask), _p(dU), _p(lost))
     return float(L), dU, int(lost[0])
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (0: keep); returns the number in use."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def splitmix64(state: int) -> int:

@@ -905,6 +905,19 @@ int orc_transfer(const orc_mesh *m, const orc_store *src, orc_store *dst, int64_
     return 0;
 }
 
+/* Threads of the OpenMP loops (timing of the oracle only; results do not
+ * depend on it).  Returns the number in use afterwards. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* counter-based random numbers: SplitMix64 (Steele, Lea, Flood 2014)   */
 /* ------------------------------------------------------------------ */

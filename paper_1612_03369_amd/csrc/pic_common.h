@@ -456,28 +456,32 @@ __device__ __forceinline__ void eval_q2_ijk(gptr<typename NodeVec<D, T>::type> U
 // earlier point of the step was inside the domain: only then is the point
 // tested for the near-boundary band (|y - lo| or |y - hi| below 1e-10 h on
 // some axis, inside or outside), as a step that stops at its first point
-// outside the domain would test it.  Reference coordinates s - i are accurate
-// to a few ulps of s, which only feeds the field evaluation; stored locations
-// use locate_uniform.
+// outside the domain would test it.  The band test runs only for points with
+// s below NEAR_PRE or above n - NEAR_PRE on some axis, which every point in
+// the band is (|s| and |s - n| exceed the band by at most a few ulps of n),
+// so the common case costs two comparisons per axis.  Reference coordinates
+// s - i are accurate to a few ulps of s, which only feeds the field
+// evaluation; stored locations use locate_uniform.
+constexpr double NEAR_PRE = 1e-6;
+template <int D> __device__ __forceinline__ bool near_boundary(const MeshDev &m, const double *y);
 template <int D>
 __device__ __forceinline__ bool locate_stage(const MeshDev &m, const double *y, int ijk[3], double *t, bool &near,
                                              bool live)
 {
-    bool inside = true, nb = false;
+    bool inside = true, maybe = false;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double d = y[a] - m.lo[a];
-        const double s = d * m.inv_h[a];
+        const double s = (y[a] - m.lo[a]) * m.inv_h[a];
         const double n = (double)m.n[a];
         inside &= (s >= 0.0) & (s <= n);
-        nb |= (fabs(d) < m.bnd_tol[a]) | (fabs(y[a] - m.hi[a]) < m.bnd_tol[a]);
+        maybe |= (s < NEAR_PRE) | (s > n - NEAR_PRE);
         int i = (int)floor(s);
         i = i >= m.n[a] ? m.n[a] - 1 : (i < 0 ? 0 : i);
         t[a] = s - (double)i;
         ijk[a] = i;
     }
     if constexpr (D == 2) ijk[2] = 0;
-    near |= live & nb;
+    if (maybe & live) near |= near_boundary<D>(m, y);
     return inside;
 }
 

@@ -189,6 +189,70 @@ __global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ 
     }
 }
 
+/*
+ * The same destinations computed by each wavefront on its own, with no
+ * workgroup barrier: a wave takes a run of up to 16 consecutive cells of the
+ * tile (their particles are consecutive), locates each particle's cell from
+ * the run's cell starts, and ranks the stayers of the run with a ballot per
+ * 64 particles (the stayers of a cell are the run's stayers minus those of
+ * its earlier cells, whose counts are known).  Arrivals take their slot from
+ * the destination cell's atomic cursor as above.
+ */
+constexpr int PLACE_RUN = 16;
+__global__ __launch_bounds__(BLOCK) void k_place_waves(const ProblemDev *__restrict__ probs,
+                                                       const WorkItem *__restrict__ work, int n_work)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
+        const int w = xcd_item(wb, n_work);
+        if (w >= n_work) continue;
+        const WorkItem wi = work[w];
+        const ProblemDev &P = probs[wi.problem];
+        const StoreDev cur = P.store[P.cur];
+        const StoreDev nxt = P.store[1 - P.cur];
+        const uint32_t PIC_G *keys = P.scr.key[P.cur];
+        for (int r0 = wi.c0 + wv * PLACE_RUN; r0 < wi.c1; r0 += (BLOCK / 64) * PLACE_RUN) {
+            const int nr = min(PLACE_RUN, wi.c1 - r0);
+            // lane q <= nr: old start of cell r0 + q (lane nr: the run's end);
+            // lane q < nr: its new start and its stayers
+            int a_q = 0, b_q = 0, s_q = 0;
+            if (lane <= nr) a_q = cur.cs[r0 + lane];
+            if (lane < nr) {
+                b_q = nxt.cs[r0 + lane];
+                s_q = P.scr.n_stay[r0 + lane];
+            }
+            int ex = s_q;
+#pragma unroll
+            for (int o = 1; o < PLACE_RUN; o <<= 1) {
+                const int v = __shfl_up(ex, o, 64);
+                if (lane >= o) ex += v;
+            }
+            ex -= s_q;                                  // stayers of the run's earlier cells
+            const int p0 = __shfl(a_q, 0, 64), p1 = __shfl(a_q, nr, 64);
+            int carry = 0;
+            for (int base = p0; base < p1; base += 64) {
+                const int pp = base + lane;
+                const bool valid = pp < p1;
+                int c = 0;                              // last cell of the run starting at or before pp
+#pragma unroll
+                for (int step = PLACE_RUN / 2; step >= 1; step >>= 1) {
+                    const int t = c + step;
+                    const int v = __shfl(a_q, t, 64);
+                    if (t < nr && v <= pp) c = t;
+                }
+                const uint32_t key = valid ? keys[pp] : LOST;
+                const bool stay = valid && key == (uint32_t)(r0 + c);
+                const unsigned long long mm = __ballot(stay);
+                const int bc = __shfl(b_q, c, 64), ec = __shfl(ex, c, 64);
+                if (stay) P.scr.src[bc + carry + __popcll(mm & below) - ec] = pp;
+                else if (key != LOST) P.scr.src[atomicAdd(&P.scr.cursor[key], 1)] = pp;
+                carry += __popcll(mm);
+            }
+        }
+    }
+}
+
 // Runs of equal keys among consecutive lanes of a wavefront (LOST = no key):
 // the lane's run starts at lane `head` and ends before lane `next`.  Every
 // lane of the wavefront must call it.
@@ -267,6 +331,49 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 // (the positions are distinct) is its slot; beyond what LDS holds, the ranks
 // are counted over LDS-sized tiles (n^2 / 256 LDS reads per thread).
 constexpr int FIX_LDS = 32;
+
+// Sort a[0..nn) (distinct values) by the whole workgroup: each value's rank
+// among the others is its place.  In LDS while the values and their sorted
+// copy fit (s_v holds FIX_LDS * BLOCK ints), else counted over LDS-sized tiles
+// with the sorted list built in t[0..nn) (memory unused until the next
+// advect writes it) and copied back.  Every thread of the workgroup calls it.
+__device__ void wg_rank_sort(int32_t PIC_G *a, int nn, int32_t PIC_G *t, int32_t *s_v)
+{
+    if (2 * nn <= FIX_LDS * BLOCK) {
+        int32_t *v = s_v, *o = s_v + nn;
+        for (int q = threadIdx.x; q < nn; q += BLOCK) v[q] = a[q];
+        __syncthreads();
+        for (int q = threadIdx.x; q < nn; q += BLOCK) {
+            const int32_t x = v[q];
+            int r = 0;
+            for (int j = 0; j < nn; ++j) r += v[j] < x;
+            o[r] = x;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = o[q];
+        __syncthreads();
+        return;
+    }
+    constexpr int TILE = FIX_LDS * BLOCK;
+    for (int q0 = 0; q0 < nn; q0 += BLOCK) {
+        const int q = q0 + (int)threadIdx.x;
+        const int32_t x = q < nn ? a[q] : 0;
+        int r = 0;
+        for (int j0 = 0; j0 < nn; j0 += TILE) {
+            const int m = min(TILE, nn - j0);
+            __syncthreads();
+            for (int j = threadIdx.x; j < m; j += BLOCK) s_v[j] = a[j0 + j];
+            __syncthreads();
+            if (q < nn)
+                for (int j = 0; j < m; ++j) r += s_v[j] < x;
+        }
+        if (q < nn) t[r] = x;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = t[q];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ probs, const RangeItem *__restrict__ items,
                                                int n_items)
 {
@@ -325,48 +432,9 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
         }
         __syncthreads();
         const int nbig = s_nbig;
-        for (int c = 0; c < nbig; ++c) {
-            const int nn = s_big_n[c];
-            auto a = (gptr_mut<int32_t>)(P.scr.src + s_big_b[c]);
-            if (2 * nn <= FIX_LDS * BLOCK) {
-                int32_t *v = s_v, *o = s_v + nn;
-                for (int q = threadIdx.x; q < nn; q += BLOCK) v[q] = a[q];
-                __syncthreads();
-                for (int q = threadIdx.x; q < nn; q += BLOCK) {
-                    const int32_t x = v[q];
-                    int r = 0;
-                    for (int j = 0; j < nn; ++j) r += v[j] < x;
-                    o[r] = x;
-                }
-                __syncthreads();
-                for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = o[q];
-                __syncthreads();
-            } else {
-                // more arrivals than LDS holds: the same ranks, counted over
-                // LDS-sized tiles of the cell's slots, with the sorted list
-                // built in the other buffer's key array at the same indices
-                // (unused until the next advect writes it) and copied back
-                auto t = (gptr_mut<int32_t>)((int32_t *)P.scr.key[1 - P.cur] + s_big_b[c]);
-                constexpr int TILE = FIX_LDS * BLOCK;
-                for (int q0 = 0; q0 < nn; q0 += BLOCK) {
-                    const int q = q0 + (int)threadIdx.x;
-                    const int32_t x = q < nn ? a[q] : 0;
-                    int r = 0;
-                    for (int j0 = 0; j0 < nn; j0 += TILE) {
-                        const int m = min(TILE, nn - j0);
-                        __syncthreads();
-                        for (int j = threadIdx.x; j < m; j += BLOCK) s_v[j] = a[j0 + j];
-                        __syncthreads();
-                        if (q < nn)
-                            for (int j = 0; j < m; ++j) r += s_v[j] < x;
-                    }
-                    if (q < nn) t[r] = x;
-                }
-                __syncthreads();
-                for (int q = threadIdx.x; q < nn; q += BLOCK) a[q] = t[q];
-                __syncthreads();
-            }
-        }
+        for (int c = 0; c < nbig; ++c)
+            wg_rank_sort((gptr_mut<int32_t>)(P.scr.src + s_big_b[c]), s_big_n[c],
+                         (gptr_mut<int32_t>)((int32_t *)P.scr.key[1 - P.cur] + s_big_b[c]), s_v);
         __syncthreads();
     }
 }
