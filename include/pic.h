@@ -233,6 +233,18 @@ PIC_API pic_status pic_seed_per_cell(pic_ctx *ctx, const int32_t *counts, uint64
  * PIC_ENONFINITE for a non-finite density. */
 PIC_API pic_status pic_seed_mh(pic_ctx *ctx, const int32_t *counts, const double *rho, int32_t J, uint64_t seed,
                                uint32_t first_id, int64_t *longest_run);
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): pic_seed_mh with the same arguments and results,
+ * bit for bit, that allocates nothing.  Its staging (the per-cell starts, the
+ * packed density, flags and the longest run) lives in a fixed 16 MiB device
+ * array of the library, one per GPU, held until the process ends: meshes
+ * needing more (256 + 4 (n_cells + 1) rounded up to 256, plus 16 bytes per
+ * node in 2D or 32 in 3D) are rejected with PIC_EINVAL.  Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on one GPU (several
+ * threads or streams) race; the array keeps the last call's contents.  Like
+ * pic_seed_mh it synchronises the context's stream. */
+PIC_API pic_status pic_seed_mh_static(pic_ctx *ctx, const int32_t *counts, const double *rho, int32_t J, uint64_t seed,
+                                      uint32_t first_id, int64_t *longest_run);
 /* Prescribed locations (Sec. 2.2, prescribed particle locations): locate each
  * x (device [dim][n]) in the mesh, drop points outside the domain, and store
  * the rest sorted by (cell, input order).  Properties as above. */

@@ -312,6 +312,19 @@ class Problem:
                                        C.byref(longest)))
         return longest.value
 
+    def seed_mh_static(self, counts, rho, J, seed, first_id=0):
+        """seed_mh for callers that cannot allocate: counts (int32 [n_cells]) and rho (float64 [n_nodes])
+        are device tensors already; the library stages everything in its fixed device scratch."""
+        torch = _torch()
+        if counts.dtype != torch.int32 or rho.dtype != torch.float64 or not (counts.is_cuda and rho.is_cuda):
+            raise ValueError("counts must be int32 and rho float64 device tensors")
+        if counts.numel() != self.n_cells or rho.numel() != self.n_nodes:
+            raise ValueError("counts / rho sizes do not match the mesh")
+        longest = C.c_int64()
+        self._chk(self.lib.pic_seed_mh_static(self.h, _ptr(counts), _ptr(rho), int(J), int(seed), int(first_id),
+                                              C.byref(longest)))
+        return longest.value
+
     # ------------------------------------------------------------- adjoint
     def adjoint_workspace(self, n_steps, ckpt_every):
         torch = _torch()

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -26,6 +27,21 @@ struct ProfEvent {
     hipEvent_t a, b;
 };
 
+}  // namespace
+
+// Fixed device scratch of pic_seed_mh_static (the generation call for
+// callers that cannot allocate): header words, the cell starts being built
+// and the packed density.  Every GPU the library runs on holds its own copy
+// until the process ends.  Its address on each device is looked up once, at
+// the first pic_create on that device; host code uses that address, never
+// the symbol itself.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+void *g_scratch_ptr[STATIC_MAX_DEVICES];
+hipError_t g_scratch_err[STATIC_MAX_DEVICES];
+std::once_flag g_scratch_once[STATIC_MAX_DEVICES];
 }  // namespace
 
 struct pic_ctx {
@@ -448,6 +464,11 @@ extern "C" pic_status pic_create(pic_ctx **out, int device, void *stream)
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PIC_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return PIC_EDEVICE;
+    if (device < STATIC_MAX_DEVICES)
+        std::call_once(g_scratch_once[device], [device] {
+            g_scratch_err[device] = hipGetSymbolAddress(&g_scratch_ptr[device], HIP_SYMBOL(scratch));
+            if (g_scratch_err[device] != hipSuccess) g_scratch_ptr[device] = nullptr;
+        });
     pic_ctx *c = new pic_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -1154,6 +1175,31 @@ extern "C" pic_status pic_interpolate_points(pic_ctx *c, int32_t kind, const dou
 // Metropolis-Hastings generation
 // ===========================================================================
 namespace {
+// Pack the density into the node-vector layout R (flag: zeroed by the
+// caller, set for a non-finite value), then run the chains; synchronises.
+template <int D>
+pic_status seed_mh_kernels(pic_ctx *c, const double *rho, int J, uint64_t seed, uint32_t first_id,
+                           typename NodeVec<D, double>::type *R, int *flag, unsigned long long *d_longest)
+{
+    const int64_t nn = c->mesh.n_nodes;
+    hipLaunchKernelGGL(k_pack_density<D>, dim3((unsigned)((nn + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, c->stream, rho, nn, R, flag);
+    int hflag = 0;
+    if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PIC_EDEVICE, "density copy");
+    if (hflag) return fail(c, PIC_ENONFINITE, "density has NaN or infinite values");
+    const unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK - 1) / BLOCK);
+    ProblemDev *dp = c->d_prob;
+    switch (c->mesh.kind) {
+    case MESH_UNIFORM: hipLaunchKernelGGL((k_seed_mh<D, MESH_UNIFORM>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
+    case MESH_DISPLACED: hipLaunchKernelGGL((k_seed_mh<D, MESH_DISPLACED>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
+    default:
+        if constexpr (D == 3) hipLaunchKernelGGL((k_seed_mh<3, MESH_OCTREE>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(c, PIC_EDEVICE, "seed_mh launch");
+    return PIC_OK;
+}
+
 template <int D>
 pic_status seed_mh_launch(pic_ctx *c, const double *rho, int J, uint64_t seed, uint32_t first_id,
                           unsigned long long *d_longest)
@@ -1168,29 +1214,12 @@ pic_status seed_mh_launch(pic_ctx *c, const double *rho, int J, uint64_t seed, u
         hipFree(R);
         return s;
     }
-    auto done = [&](pic_status st) {
-        hipStreamSynchronize(c->stream);
-        hipFree(R);
-        hipFree(flag);
-        return st;
-    };
-    if (hipMemsetAsync(flag, 0, sizeof(int), c->stream) != hipSuccess) return done(fail(c, PIC_EDEVICE, "memset"));
-    hipLaunchKernelGGL(k_pack_density<D>, dim3((unsigned)((nn + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, c->stream, rho, nn, R, flag);
-    int hflag = 0;
-    if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-        return done(fail(c, PIC_EDEVICE, "density copy"));
-    if (hflag) return done(fail(c, PIC_ENONFINITE, "density has NaN or infinite values"));
-    const unsigned grid = (unsigned)((c->mesh.n_cells + BLOCK - 1) / BLOCK);
-    ProblemDev *dp = c->d_prob;
-    switch (c->mesh.kind) {
-    case MESH_UNIFORM: hipLaunchKernelGGL((k_seed_mh<D, MESH_UNIFORM>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
-    case MESH_DISPLACED: hipLaunchKernelGGL((k_seed_mh<D, MESH_DISPLACED>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest); break;
-    default:
-        if constexpr (D == 3) hipLaunchKernelGGL((k_seed_mh<3, MESH_OCTREE>), dim3(grid), dim3(BLOCK), 0, c->stream, dp, 0, R, J, seed, first_id, d_longest);
-    }
-    if (hipGetLastError() != hipSuccess) return done(fail(c, PIC_EDEVICE, "seed_mh launch"));
-    return done(PIC_OK);
+    if (hipMemsetAsync(flag, 0, sizeof(int), c->stream) != hipSuccess) s = fail(c, PIC_EDEVICE, "memset");
+    if (!s) s = seed_mh_kernels<D>(c, rho, J, seed, first_id, R, flag, d_longest);
+    hipStreamSynchronize(c->stream);
+    hipFree(R);
+    hipFree(flag);
+    return s;
 }
 }  // namespace
 
@@ -1233,6 +1262,65 @@ extern "C" pic_status pic_seed_mh(pic_ctx *c, const int32_t *counts, const doubl
     }
     hipFree(d_longest);
     return s;
+}
+
+extern "C" pic_status pic_seed_mh_static(pic_ctx *c, const int32_t *counts, const double *rho, int32_t J, uint64_t seed,
+                                         uint32_t first_id, int64_t *longest_run)
+{
+    pic_status s = require_ready(c, false);
+    if (s) return s;
+    if (!counts || !rho) return fail(c, PIC_EINVAL, "null argument");
+    if (J < 1) return fail(c, PIC_EINVAL, "J must be at least 1");
+    if (c->device >= STATIC_MAX_DEVICES || !g_scratch_ptr[c->device])
+        return fail(c, PIC_EDEVICE, "no address of the static scratch on device %d: %s", c->device,
+                    c->device < STATIC_MAX_DEVICES ? hipGetErrorString(g_scratch_err[c->device]) : "device index too large");
+    hipSetDevice(c->device);
+    const int64_t nc = c->mesh.n_cells, nn = c->mesh.n_nodes;
+    const size_t vbytes = c->mesh.dim == 3 ? sizeof(double4) : sizeof(double2);
+    const size_t cs_off = 256, r_off = cs_off + align256(sizeof(int32_t) * (size_t)(nc + 1));
+    const size_t need = r_off + vbytes * (size_t)nn;
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(c, PIC_EINVAL, "the mesh (%lld cells, %lld nodes) needs %zu bytes of scratch; the static scratch holds %zu",
+                    (long long)nc, (long long)nn, need, STATIC_SCRATCH_BYTES);
+    unsigned char *base = (unsigned char *)g_scratch_ptr[c->device];
+    int32_t *flags = (int32_t *)base;                       // [0] non-finite density, [1] negative count
+    auto *d_longest = (unsigned long long *)(base + 8);
+    auto *d_total = (int64_t *)(base + 16);
+    auto *d_cs = (int32_t *)(base + cs_off);
+    // cell starts = exclusive scan of the counts, built in the scratch and
+    // copied to the store only once the counts are known to fit
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, c->stream, base, (int64_t)24);
+    hipLaunchKernelGGL(k_counts_scan, dim3(1), dim3(BLOCK), 0, c->stream, counts, nc, d_cs, d_total, flags + 1);
+    struct {
+        int32_t flag[2];
+        unsigned long long longest;
+        int64_t total;
+    } h{};
+    static_assert(sizeof(h) == 24, "header layout");
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&h, base, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h.flag[1]) return fail(c, PIC_EINVAL, "negative count");
+    if (h.total > c->store.capacity)
+        return fail(c, PIC_ECAPACITY, "%lld particles exceed capacity %lld", (long long)h.total, (long long)c->store.capacity);
+    if ((uint64_t)first_id + (uint64_t)h.total > 0xFFFFFFFFull) return fail(c, PIC_EINVAL, "ids would overflow 32 bits");
+    int32_t cur = 0;
+    if ((s = pic_current_buffer(c, &cur))) return s;
+    HIPCHK(c, hipMemcpyAsync(c->store.cell_start[cur], d_cs, sizeof(int32_t) * (size_t)(nc + 1), hipMemcpyDeviceToDevice,
+                             c->stream));
+    const int64_t nid = 8 * (1 + STAT_STRIPES);
+    hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((nid + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, c->stream,
+                       (unsigned char *)c->scr.next_id, nid);
+    s = c->mesh.dim == 2 ? seed_mh_kernels<2>(c, rho, J, seed, first_id, (double2 *)(base + r_off), flags, d_longest)
+                         : seed_mh_kernels<3>(c, rho, J, seed, first_id, (double4 *)(base + r_off), flags, d_longest);
+    if (s) return s;
+    hipLaunchKernelGGL(k_reduce_next_id, dim3(1), dim3(STAT_STRIPES), 0, c->stream, (const ProblemDev *)c->d_prob);
+    unsigned long long hl = 0;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&hl, d_longest, sizeof(hl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (longest_run) *longest_run = (int64_t)hl;
+    return PIC_OK;
 }
 
 // ===========================================================================

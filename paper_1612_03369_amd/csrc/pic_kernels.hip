@@ -952,6 +952,45 @@ __global__ void k_pack_density(const double *__restrict__ rho, int64_t nn, typen
     R[g] = r;
 }
 
+// Exclusive scan of per-cell counts by one workgroup (cell starts of a
+// generation call): each thread sums a contiguous run of cells, a workgroup
+// scan offsets the runs.  out[nc] = total, *total = the same as int64, and
+// *negative = 1 if a count is negative.
+__global__ __launch_bounds__(BLOCK) void k_counts_scan(const int32_t *__restrict__ counts, int64_t nc, int32_t *out,
+                                                       int64_t *total, int32_t *negative)
+{
+    __shared__ int64_t s_tmp[BLOCK / 64];
+    const int64_t per = (nc + BLOCK - 1) / BLOCK;
+    const int64_t b = (int64_t)threadIdx.x * per, e = b + per < nc ? b + per : nc;
+    int64_t sum = 0;
+    bool neg = false;
+    for (int64_t K = b; K < e; ++K) {
+        const int32_t v = counts[K];
+        neg |= v < 0;
+        sum += v > 0 ? v : 0;
+    }
+    int64_t tot;
+    int64_t run = block_scan_i64(sum, s_tmp, tot);
+    for (int64_t K = b; K < e; ++K) {
+        out[K] = (int32_t)run;
+        const int32_t v = counts[K];
+        run += v > 0 ? v : 0;
+    }
+    if (neg) atomicOr(negative, 1);
+    if (threadIdx.x == 0) {
+        out[nc] = (int32_t)tot;
+        *total = tot;
+    }
+}
+
+// Zero n bytes (a kernel rather than a memset, so that it can sit anywhere in
+// a stream, graphs included).
+__global__ void k_zero_bytes(unsigned char *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 /*
  * Metropolis-Hastings generation (Sec. 2.2), one thread per cell K: a chain
  * in the reference cell with a proposal uniform in it, starting at its
