@@ -18,13 +18,17 @@ template <int S> BlockFn pick_f(int prec, bool fused, bool ode, bool ti)
     if (prec == PIC_F32) return fused ? pick<S, float, true>(ode, ti) : pick<S, float, false>(ode, ti);
     return fused ? pick<S, double, true>(ode, ti) : pick<S, double, false>(ode, ti);
 }
-template <int S, int V> BlockFn shape() { return k_advect_blk<2, S, double, SHAPES2[V][0], SHAPES2[V][1], 1, false>; }
-template <int S> BlockFn shape_v(int variant)
+template <int S, int V> BlockFn shape(bool fused)
+{
+    if (fused) return k_advect_blk<2, S, double, SHAPES2[V][0], SHAPES2[V][1], 1, true>;
+    return k_advect_blk<2, S, double, SHAPES2[V][0], SHAPES2[V][1], 1, false>;
+}
+template <int S> BlockFn shape_v(int variant, bool fused)
 {
     switch (variant) {
-    case 0: return shape<S, 0>();
-    case 1: return shape<S, 1>();
-    case 2: return shape<S, 2>();
+    case 0: return shape<S, 0>(fused);
+    case 1: return shape<S, 1>(fused);
+    case 2: return shape<S, 2>(fused);
     }
     return nullptr;
 }
@@ -40,12 +44,12 @@ BlockFn block_kernel_2(int scheme, int prec, bool fused, bool ode, bool ti)
     return nullptr;
 }
 
-BlockFn batch_block_kernel_2(int scheme, int variant)
+BlockFn batch_block_kernel_2(int scheme, int variant, bool fused)
 {
     switch (scheme) {
-    case PIC_EULER: return shape_v<1>(variant);
-    case PIC_RK2: return shape_v<2>(variant);
-    case PIC_RK4: return shape_v<4>(variant);
+    case PIC_EULER: return shape_v<1>(variant, fused);
+    case PIC_RK2: return shape_v<2>(variant, fused);
+    case PIC_RK4: return shape_v<4>(variant, fused);
     }
     return nullptr;
 }

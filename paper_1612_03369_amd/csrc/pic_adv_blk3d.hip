@@ -14,13 +14,17 @@ template <int S, bool F> BlockFn pick(bool ode, bool ti)
     return k_advect_blk<3, S, double, X, Y, Z, F, false, false>;
 }
 template <int S> BlockFn pick_f(bool fused, bool ode, bool ti) { return fused ? pick<S, true>(ode, ti) : pick<S, false>(ode, ti); }
-template <int S, int V> BlockFn shape() { return k_advect_blk<3, S, double, SHAPES3[V][0], SHAPES3[V][1], SHAPES3[V][2], false>; }
-template <int S> BlockFn shape_v(int variant)
+template <int S, int V> BlockFn shape(bool fused)
+{
+    if (fused) return k_advect_blk<3, S, double, SHAPES3[V][0], SHAPES3[V][1], SHAPES3[V][2], true>;
+    return k_advect_blk<3, S, double, SHAPES3[V][0], SHAPES3[V][1], SHAPES3[V][2], false>;
+}
+template <int S> BlockFn shape_v(int variant, bool fused)
 {
     switch (variant) {
-    case 0: return shape<S, 0>();
-    case 1: return shape<S, 1>();
-    case 2: return shape<S, 2>();
+    case 0: return shape<S, 0>(fused);
+    case 1: return shape<S, 1>(fused);
+    case 2: return shape<S, 2>(fused);
     }
     return nullptr;
 }
@@ -36,12 +40,12 @@ BlockFn block_kernel_3d(int scheme, bool fused, bool ode, bool ti)
     return nullptr;
 }
 
-BlockFn batch_block_kernel_3(int scheme, int variant)
+BlockFn batch_block_kernel_3(int scheme, int variant, bool fused)
 {
     switch (scheme) {
-    case PIC_EULER: return shape_v<1>(variant);
-    case PIC_RK2: return shape_v<2>(variant);
-    case PIC_RK4: return shape_v<4>(variant);
+    case PIC_EULER: return shape_v<1>(variant, fused);
+    case PIC_RK2: return shape_v<2>(variant, fused);
+    case PIC_RK4: return shape_v<4>(variant, fused);
     }
     return nullptr;
 }

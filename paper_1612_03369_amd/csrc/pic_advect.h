@@ -1029,9 +1029,10 @@ using AdvectFn = void (*)(const ProblemDev *, const WorkItem *, int);
 BlockFn block_kernel_2(int scheme, int prec, bool fused, bool ode, bool ti);
 BlockFn block_kernel_3f(int scheme, bool fused, bool ode, bool ti);
 BlockFn block_kernel_3d(int scheme, bool fused, bool ode, bool ti);
-// Double-precision unfused block kernels of batch shape `variant`.
-BlockFn batch_block_kernel_2(int scheme, int variant);
-BlockFn batch_block_kernel_3(int scheme, int variant);
+// Double-precision block kernels of batch shape `variant` (fused: the
+// gather + advect form, as block_kernel).
+BlockFn batch_block_kernel_2(int scheme, int variant, bool fused);
+BlockFn batch_block_kernel_3(int scheme, int variant, bool fused);
 // Generic per-tile kernels (any mesh kind).
 AdvectFn advect_kernel_2(int scheme, int prec, int kind, bool ode, bool ti);
 AdvectFn advect_kernel_3(int scheme, int prec, int kind, bool ode, bool ti);
@@ -1045,9 +1046,9 @@ inline BlockFn block_kernel(int dim, int scheme, int prec, bool fused, bool ode,
     if (dim == 2) return block_kernel_2(scheme, prec, fused, ode, ti);
     return prec == PIC_F32 ? block_kernel_3f(scheme, fused, ode, ti) : block_kernel_3d(scheme, fused, ode, ti);
 }
-inline BlockFn batch_block_kernel(int dim, int scheme, int variant)
+inline BlockFn batch_block_kernel(int dim, int scheme, int variant, bool fused)
 {
-    return dim == 2 ? batch_block_kernel_2(scheme, variant) : batch_block_kernel_3(scheme, variant);
+    return dim == 2 ? batch_block_kernel_2(scheme, variant, fused) : batch_block_kernel_3(scheme, variant, fused);
 }
 
 }  // namespace pic
