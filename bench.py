@@ -29,6 +29,8 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 # byte counters of the dominant kernel, taken by --summarize-traffic from two rocprofv3 --pmc runs
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_gather_advect_uniform64_rk4_f32.json")
 DOMINANT_KERNEL = "k_advect_blk<3, 4, float, 4, 4, 4, true, false, false>"
+ADJOINT_TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_adjoint_blk_adjoint32_rk4.json")
+ADJOINT_KERNEL = "k_adjoint_blk<3, 4, 4, 2, 2>"
 COPY_BYTES = 64 * 1024 * 1024 * 4          # the calibration copy below: 256 MiB read, 256 MiB written
 
 
@@ -74,12 +76,12 @@ def _copy_kib(per_kernel):
     return statistics.median(v for v in vals if v >= 0.5 * top)
 
 
-def summarize_traffic(fetch_dir, write_dir, command):
-    """HBM bytes per launch of the dominant kernel from FETCH_SIZE and WRITE_SIZE runs, each scaled by what the
-    same counter reads for the 256 MiB device copy of the same run."""
+def summarize_traffic(fetch_dir, write_dir, command, kernel=DOMINANT_KERNEL):
+    """HBM bytes per launch of one kernel (the dominant one by default) from FETCH_SIZE and WRITE_SIZE runs, each
+    scaled by what the same counter reads for the 256 MiB device copy of the same run."""
     fetch = _pmc_per_dispatch(fetch_dir, "FETCH_SIZE")
     write = _pmc_per_dispatch(write_dir, "WRITE_SIZE")
-    dom = [k for k in fetch if DOMINANT_KERNEL in k]
+    dom = [k for k in fetch if kernel in k]
     if len(dom) != 1:
         raise SystemExit(f"dominant kernel not found once in {fetch_dir}: {dom}")
     dom = dom[0]
@@ -134,7 +136,7 @@ def summarize_counters(run_dir, title, command):
     print(f"# rocprofv3 counter summary: {title}")
     print(f"# command: {command}")
     print("# per kernel: dispatches, mean duration, mean of each counter per dispatch, wait and VALU-issue fractions")
-    keep = ("k_advect_blk", "k_place", "k_fix", "k_scan", "k_gather")
+    keep = ("k_advect_blk", "k_place", "k_fix", "k_scan", "k_gather", "k_adjoint_blk")
     for name in sorted(acc, key=lambda n: -sum(acc[n]["duration_ns"])):
         if not any(k in name for k in keep):
             continue
@@ -148,19 +150,26 @@ def summarize_counters(run_dir, title, command):
                 print(f"    wait_fraction {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.3f}")
             if "SQ_ACTIVE_INST_VALU" in c:
                 print(f"    valu_issue_fraction {c['SQ_ACTIVE_INST_VALU'] / c['SQ_WAVE_CYCLES']:.3f}")
+        for prec in ("F32", "F64"):
+            names = [f"SQ_INSTS_VALU_{op}_{prec}" for op in ("FMA", "MUL", "ADD")]
+            if all(n in c for n in names):
+                # wave instructions x 64 lanes: an upper bound (partly masked waves count in full)
+                flop = 64.0 * (2 * c[names[0]] + c[names[1]] + c[names[2]])
+                dur = sum(acc[name]["duration_ns"]) / len(acc[name]["duration_ns"])
+                print(f"    {prec.lower()}_flop_upper {flop:.4g}  ({flop / dur / 1e3:.2f} TFLOP/s over the mean duration)")
 
 
-def measured_traffic():
-    """Bytes per launch of the dominant kernel from the committed counter summary, or None when the summary is
-    missing or was taken on other sources."""
+def measured_traffic(path=TRAFFIC_FILE):
+    """Bytes per launch of a kernel (the dominant one by default) from its committed counter summary, or None when
+    the summary is missing or was taken on other sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None, "no counter summary"
     if rec.get("source_sha256") != source_digest():
         return None, "counter summary taken on other sources"
-    return rec["traffic_bytes_per_launch"], TRAFFIC_FILE
+    return rec["traffic_bytes_per_launch"], os.path.relpath(path, REPO)
 
 
 def bytes_per_particle(kernel, dim=3, prop_bytes=12):
@@ -339,9 +348,29 @@ def bench_adjoint(args):
         p.adjoint(dl, ws, dU)
 
     both = timed(fwd_bwd)
+    # the reverse-step kernel alone: its mean launch time from the library's HIP events, priced at the bytes it
+    # must move (per particle-step: x, x-hat, cell, dst and lambda' read, lambda written; per launch: the field
+    # window's nodes and dU read and written once)
+    p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
+    p.profile(True)
+    fwd_bwd()
+    torch.cuda.synchronize()
+    ms, cnt = p.profile_read("adjoint_step")
+    p.profile(False)
+    per_particle = 8 * 3 + 8 * 3 + 4 + 4 + 8 * 3 + 8 * 3
+    per_node = 32 + 2 * 8 * 3
+    bytes_launch = n0 * per_particle + mesh.n_nodes * per_node
+    avg_us = 1e3 * ms / max(cnt, 1)
+    traffic, traffic_src = measured_traffic(ADJOINT_TRAFFIC_FILE)
     r = {"workload": cfg["name"], "particles": n0, "forward_ms": fwd * 1e3, "forward_plus_adjoint_ms": both * 1e3,
-         "ratio": both / fwd}
-    log(f"[bench] adjoint: forward {fwd * 1e3:.1f} ms, checkpointed forward + adjoint {both * 1e3:.1f} ms")
+         "ratio": both / fwd,
+         "reverse_kernel": {"name": "k_adjoint_blk", "launches": cnt, "avg_launch_us": avg_us,
+                            "bytes_per_launch": bytes_launch, "achieved_gbs": bytes_launch / (avg_us * 1e3),
+                            "hbm_frac": bytes_launch / (avg_us * 1e-6) / 8e12,
+                            "bytes_model": f"{per_particle} B per particle-step + {per_node} B per node",
+                            "traffic": traffic, "traffic_source": traffic_src}}
+    log(f"[bench] adjoint: forward {fwd * 1e3:.1f} ms, checkpointed forward + adjoint {both * 1e3:.1f} ms; "
+        f"reverse step {avg_us:.0f} us x {cnt} ({bytes_launch / (avg_us * 1e3):.0f} GB/s of algorithmic bytes)")
     p.close()
     return r
 
@@ -712,13 +741,15 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="print the counter summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--traffic-kernel", default=DOMINANT_KERNEL,
+                    help="kernel whose bytes --summarize-traffic reports (default: the fused advect)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("RUN_DIR", "TITLE", "COMMAND"),
                     help="print a per-kernel SQ counter summary of a rocprofv3 --pmc run (for profiles/)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "TITLE", "COMMAND"),
                     help="print the per-kernel summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
     if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic)
+        summarize_traffic(*args.summarize_traffic, kernel=args.traffic_kernel)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
