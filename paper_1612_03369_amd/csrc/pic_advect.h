@@ -525,15 +525,99 @@ __device__ __forceinline__ void eval_blk(const MeshDev &m, gptr<typename NodeVec
     }
 }
 
+// x-Horner form of the single-precision 3D evaluation.  Along x, the Q2 row
+// through nodes u0, u1, u2 (reference x = 0, 1/2, 1) is the quadratic
+// a + t (b + t c) with a = u0, b = 4 u1 - 3 u0 - u2, c = 2 (u0 - 2 u1 + u2):
+// two FMAs per row and component instead of three plus the x basis.  The
+// y and z directions keep the Lagrange sum.  The coefficients are computed by
+// these functions only, whether staged in LDS or formed from the global node
+// array, so both give the same rounding.
+__device__ __forceinline__ float xh_b(float u0, float u1, float u2) { return __builtin_fmaf(4.f, u1, -__builtin_fmaf(3.f, u0, u2)); }
+__device__ __forceinline__ float xh_c(float u0, float u1, float u2) { return 2.f * __builtin_fmaf(-2.f, u1, u0 + u2); }
+__device__ __forceinline__ float xh_row(float a, float b, float c, float t)
+{
+    return __builtin_fmaf(__builtin_fmaf(c, t, b), t, a);
+}
+// Coefficients of one cell row (three float4: a, b, c; the fourth lanes unused).
+__device__ __forceinline__ void xh_coef(const float4 &u0, const float4 &u1, const float4 &u2, float4 &a, float4 &b,
+                                        float4 &c)
+{
+    a = u0;
+    b = make_float4(xh_b(u0.x, u1.x, u2.x), xh_b(u0.y, u1.y, u2.y), xh_b(u0.z, u1.z, u2.z), 0.f);
+    c = make_float4(xh_c(u0.x, u1.x, u2.x), xh_c(u0.y, u1.y, u2.y), xh_c(u0.z, u1.z, u2.z), 0.f);
+}
+// Sum over the nine rows of a cell given row(b, c3, A, B, C) loading the
+// coefficients of row (b, c3); the rows of a plane are all loaded before use.
+template <class Row> __device__ __forceinline__ void eval_xh(Row &&row, const double *tr, double *u)
+{
+    const float t0 = (float)tr[0];
+    float lb[3], lc[3];
+    lag3((float)tr[1], lb);
+    lag3((float)tr[2], lc);
+    float a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) {
+        float4 A[3], B[3], C[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) row(b, c3, A[b], B[b], C[b]);
+        __builtin_amdgcn_sched_barrier(0);
+        float r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            r0 = __builtin_fmaf(lb[b], xh_row(A[b].x, B[b].x, C[b].x, t0), r0);
+            r1 = __builtin_fmaf(lb[b], xh_row(A[b].y, B[b].y, C[b].y, t0), r1);
+            r2 = __builtin_fmaf(lb[b], xh_row(A[b].z, B[b].z, C[b].z, t0), r2);
+        }
+        a0 = __builtin_fmaf(lc[c3], r0, a0);
+        a1 = __builtin_fmaf(lc[c3], r1, a1);
+        a2 = __builtin_fmaf(lc[c3], r2, a2);
+    }
+    u[0] = (double)a0;
+    u[1] = (double)a1;
+    u[2] = (double)a2;
+}
+// The x-Horner window of a block: cell rows of the block's cells plus a
+// one-cell halo, CX cells along x by WY x WZ node rows, three float4 each.
+template <int BX, int BY, int BZ> struct XhShape {
+    using Sh = BlockShape<3, BX, BY, BZ>;
+    static constexpr int ROWS = Sh::CX * Sh::WY * Sh::WZ;
+    static constexpr int VEC = 3 * ROWS;
+};
+// Field at (ijk, t) from the x-Horner window when the cell lies in the block
+// or its halo, else from coefficients formed from the global node array.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void eval_blk_xh(const MeshDev &m, gptr<float4> Ug, const float4 *W, const int *b0,
+                                            const int ijk[3], const double *t, double *u)
+{
+    using Sh = BlockShape<3, BX, BY, BZ>;
+    const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;
+    const bool in = ((unsigned)di < (unsigned)Sh::CX) & ((unsigned)dj < (unsigned)Sh::CY) & ((unsigned)dk < (unsigned)Sh::CZ);
+    if (in) {
+        const int base = 3 * (di + Sh::CX * (2 * dj + Sh::WY * 2 * dk));
+        eval_xh([&](int b, int c3, float4 &A, float4 &B, float4 &C) {
+            const int q = base + 3 * Sh::CX * (b + Sh::WY * c3);
+            A = W[q];
+            B = W[q + 1];
+            C = W[q + 2];
+        }, t, u);
+    } else {
+        const int64_t sy = m.nnx, sz = (int64_t)m.nnx * m.nny;
+        const int64_t base = 2 * ijk[0] + sy * (2 * ijk[1]) + sz * (2 * ijk[2]);
+        eval_xh([&](int b, int c3, float4 &A, float4 &B, float4 &C) {
+            const int64_t r = base + sy * b + sz * c3;
+            xh_coef(Ug[r], Ug[r + 1], Ug[r + 2], A, B, C);
+        }, t, u);
+    }
+}
+
 // One step of one particle on a uniform mesh; ev(c, ijk, t, u) evaluates the
 // field in cell ijk at stage time code c (as advect_one_e).
 template <int D, int S, class Eval>
 __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, double dt, double *x, double *t,
-                                                   uint32_t K, bool &near)
+                                                   const int ijk[3], bool &near)
 {
-    int ijk[3], jk[3];
+    int jk[3];
     double u[3], y[3], ty[3], xn[3];
-    ijk_of<D>(m, K, ijk);
     ev(0, ijk, t, u);
     bool in = true;
     if constexpr (S == 1) {
@@ -637,14 +721,13 @@ __device__ __forceinline__ void grad_blk(const MeshDev &m, gptr<typename NodeVec
 template <int D, int S, class Eval, class Grad>
 __device__ __forceinline__ uint32_t advect_one_blk_ode(const MeshDev &m, Eval &&ev, Grad &&gr, double dt,
                                                        double alpha, double beta, double *x, double *t, double *Pp,
-                                                       uint32_t K, bool &near)
+                                                       const int ijk0[3], bool &near)
 {
     constexpr int NP = 1 + D * D;
     constexpr int NS = S == 1 ? 1 : (S == 2 ? 2 : 4);
     const double s6 = 1.0 / 6.0, s3 = 1.0 / 3.0;
-    int jk[3];
+    int jk[3] = {ijk0[0], ijk0[1], ijk0[2]};
     double u[3], G[3][3], y[3], ty[3], xn[3], k[3], Ps[NP], kP[4][NP];
-    ijk_of<D>(m, K, jk);
     bool in = true;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -719,6 +802,9 @@ __device__ __forceinline__ uint32_t advect_one_blk_ode(const MeshDev &m, Eval &&
 template <int D, typename T> struct BlkWaves {
     static constexpr int value = D == 2 ? 1 : (sizeof(T) == 4 ? (PIC_BLK_MIN_WAVES > 0 ? PIC_BLK_MIN_WAVES : 1) : 2);
 };
+#ifndef PIC_XH
+#define PIC_XH 1                    // 3D single-precision block kernels: x-Horner window (0: node window)
+#endif
 #ifndef PIC_BLK_PREFETCH
 #define PIC_BLK_PREFETCH 2          // 1: load the next particle's state while advancing this one; 2: also its gather source one step earlier
 #endif
@@ -736,13 +822,20 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
 {
     using Sh = BlockShape<D, BX, BY, BZ>;
     using V = typename NodeVec<D, T>::type;
-    __shared__ V s_w[Sh::NODES * (TI ? 2 : 1)];   // u^n window, then the u^{n+1} window
+    // single-precision 3D evaluation of a steady field reads the x-Horner
+    // window; the other forms read the node window
+    constexpr bool XH = PIC_XH && D == 3 && sizeof(T) == 4 && !ODE && !TI;
+    using Xh = XhShape<BX, BY, D == 3 ? BZ : 1>;
+    __shared__ V s_w[XH ? 1 : Sh::NODES * (TI ? 2 : 1)];   // u^n window, then the u^{n+1} window
+    __shared__ float4 s_xh[XH ? Xh::VEC : 1];
     __shared__ int s_cnt[Sh::CELLS];
     static_assert(Sh::ROWS <= 64, "one wave scans the rows of a block");
     __shared__ int s_pre_w[ADV_BLOCK / 64][Sh::ROWS + 1];
     __shared__ int s_beg_w[ADV_BLOCK / 64][Sh::ROWS];
+    __shared__ int s_cs_w[ADV_BLOCK / 64][Sh::ROWS][BX + 1];
     int *s_pre = s_pre_w[threadIdx.x >> 6];      // each wave keeps its own copy of the row runs
     int *s_beg = s_beg_w[threadIdx.x >> 6];
+    int(*s_cs)[BX + 1] = s_cs_w[threadIdx.x >> 6];   // and of the cell starts within each row
     for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
         const int w = xcd_item(wb, n_work);
         if (w >= n_work) continue;
@@ -752,7 +845,6 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
         const MeshDev &m = P.mesh;
         const StoreDev cur = P.store[P.cur];
         const StoreDev out = P.store[FUSED ? 1 - P.cur : P.cur];
-        const uint32_t *key_in = P.scr.key[P.cur];
         uint32_t *key_out = P.scr.key[FUSED ? 1 - P.cur : P.cur];
         const int64_t cap = P.cap;
         const double dt = P.dt;
@@ -764,7 +856,10 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
         StageTheta th;
         if constexpr (TI) th.init(FUSED ? *P.tau + dt : *P.tau, dt, P.dt_u);
         auto ev = [&](int c, const int *ijk, const double *tc, double *uc) {
-            eval_blk<D, T, BX, BY, BZ>(m, Ug, s_w, b0, ijk, tc, uc);
+            if constexpr (XH)
+                eval_blk_xh<BX, BY, BZ>(m, (gptr<float4>)P.u32, s_xh, b0, ijk, tc, uc);
+            else
+                eval_blk<D, T, BX, BY, BZ>(m, Ug, s_w, b0, ijk, tc, uc);
             if constexpr (TI) {
                 double u1[3];
                 eval_blk<D, T, BX, BY, BZ>(m, Ug1, s_w + Sh::NODES, b0, ijk, tc, u1);
@@ -794,6 +889,9 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
                     const int K = bi.i0 + m.n[0] * ((bi.j0 + rj) + m.n[1] * (D == 3 ? bi.k0 + rk : 0));
                     beg = out.cs[K];
                     len = out.cs[K + nx] - beg;
+                    // starts of the row's cells; columns beyond the mesh never match
+#pragma unroll
+                    for (int c = 1; c < BX; ++c) s_cs[r][c] = c < nx ? out.cs[K + c] : 0x7fffffff;
                 }
                 s_beg[r] = beg;
             }
@@ -819,19 +917,24 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
                 if (r + step < Sh::ROWS && s_pre[r + step] <= f) r += step;
             return s_beg[r] + (f - s_pre[r]);
         };
+        // The cell of the particle at position p of row r is the row's cell
+        // whose range holds p: the particle's current cell (in a fused step,
+        // the key that placed it there), so neither key nor cell is read.
+        auto column_of = [&](int r, int p) {
+            int c = 0;
+#pragma unroll
+            for (int q = 1; q < BX; ++q) c += p >= s_cs[r][q];
+            return c;
+        };
         // one-deep software prefetch of the next particle's state
-        int rn = 0, pn = 0, sn = 0;
-        int32_t Kn = 0;
-        double xn_[3] = {0, 0, 0}, tn_[3] = {0, 0, 0};
+        int rn = 0, pn = 0, sn = 0, cn = 0;
+        double xn_[3] = {0, 0, 0};
         auto fetch = [&](int f) {
             pn = locate_f(f, rn);
             sn = FUSED ? P.scr.src[pn] : pn;
-            Kn = FUSED ? (int32_t)key_in[sn] : cur.cell[sn];
+            cn = column_of(rn, pn);
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                xn_[a] = cur.x[a * cap + sn];
-                tn_[a] = cur.xr[a * cap + sn];
-            }
+            for (int a = 0; a < D; ++a) xn_[a] = cur.x[a * cap + sn];
         };
         // two-deep variant: the gather source of particle f + 2 BLOCK is loaded
         // one iteration ahead of its state
@@ -844,12 +947,9 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
             pn = pA;
             rn = rA;
             sn = sA;
-            Kn = FUSED ? (int32_t)key_in[sn] : cur.cell[sn];
+            cn = column_of(rn, pn);
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                xn_[a] = cur.x[a * cap + sn];
-                tn_[a] = cur.xr[a * cap + sn];
-            }
+            for (int a = 0; a < D; ++a) xn_[a] = cur.x[a * cap + sn];
         };
         if (PIC_BLK_PREFETCH == 2) {
             if ((int)threadIdx.x < total) {
@@ -865,7 +965,41 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
         // and are left unset.  Every thread requests all its nodes before it
         // stores the first one to LDS, so that the loads are in flight
         // together (entries beyond the mesh load node 0 and are dropped).
-        {
+        if constexpr (XH) {
+            // x-Horner window: cell row q = (cell cx of the row, node row wy,
+            // node plane wz) from the three nodes 2 (i0 - 1 + cx) + {0, 1, 2}
+            constexpr int NQ = (Xh::ROWS + ADV_BLOCK - 1) / ADV_BLOCK;
+            const int nnx = m.nnx, nny = m.nny, nnz = m.nnz;
+            float4 v0[NQ], v1[NQ], v2[NQ];
+            uint32_t ok = 0;
+            int tq = threadIdx.x;
+            asm volatile("" : "+v"(tq));
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tq + u * ADV_BLOCK;
+                const int cx = q % Sh::CX, wy = (q / Sh::CX) % Sh::WY, wz = q / (Sh::CX * Sh::WY);
+                const int gi = 2 * (bi.i0 - 1 + cx), gj = 2 * (bi.j0 - 1) + wy, gk = 2 * (bi.k0 - 1) + wz;
+                const bool in = q < Xh::ROWS && gi >= 0 && gi + 2 < nnx && gj >= 0 && gj < nny && gk >= 0 && gk < nnz;
+                const int64_t g = in ? gi + (int64_t)nnx * (gj + (int64_t)nny * gk) : 0;
+                ok |= (uint32_t)in << u;
+                const gptr<float4> U32 = (gptr<float4>)P.u32;
+                v0[u] = U32[g];
+                v1[u] = U32[in ? g + 1 : 0];
+                v2[u] = U32[in ? g + 2 : 0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tq + u * ADV_BLOCK;
+                if ((ok >> u) & 1u) {
+                    float4 A, B, C;
+                    xh_coef(v0[u], v1[u], v2[u], A, B, C);
+                    s_xh[3 * q] = A;
+                    s_xh[3 * q + 1] = B;
+                    s_xh[3 * q + 2] = C;
+                }
+            }
+        } else {
             constexpr int NQ = (Sh::NODES + ADV_BLOCK - 1) / ADV_BLOCK;
             const int nnx = m.nnx, nny = m.nny, nnz = D == 3 ? m.nnz : 1;
             using E = decltype(V{}.x);
@@ -908,13 +1042,17 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
         __syncthreads();
         for (int f = threadIdx.x; f < total; f += ADV_BLOCK) {
             if (!PIC_BLK_PREFETCH) fetch(f);
-            const int r = rn, p = pn, sidx = sn;
-            const int32_t K = Kn;
+            const int r = rn, p = pn, sidx = sn, col = cn;
+            // the particle's cell, and its reference coordinates there by the
+            // closed form that located it (on a uniform mesh they are a function
+            // of the position and the cell, so they are not read)
+            const int ijk[3] = {bi.i0 + col, bi.j0 + r % BY, D == 3 ? bi.k0 + r / BY : 0};
+            const int32_t K = (int32_t)cell_of<D>(m, ijk);
             double x[3], t[3];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 x[a] = xn_[a];
-                t[a] = tn_[a];
+                t[a] = (x[a] - fma((double)ijk[a], m.h[a], m.lo[a])) * m.inv_h[a];
             }
             if (PIC_BLK_PREFETCH == 2) {
                 if (f + ADV_BLOCK < total) stage_b();
@@ -950,10 +1088,9 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
                 Pp[0] = pin[P.ode_dmg * cap + sidx];
 #pragma unroll
                 for (int q = 0; q < D * D; ++q) Pp[1 + q] = pin[(P.ode_F + q) * cap + sidx];
-                key = advect_one_blk_ode<D, S>(m, ev, gr, dt, P.ode_alpha, P.ode_beta, x, t, Pp,
-                                                              (uint32_t)K, near);
+                key = advect_one_blk_ode<D, S>(m, ev, gr, dt, P.ode_alpha, P.ode_beta, x, t, Pp, ijk, near);
             } else {
-                key = advect_one_blk<D, S>(m, ev, dt, x, t, (uint32_t)K, near);
+                key = advect_one_blk<D, S>(m, ev, dt, x, t, ijk, near);
             }
             if (key != LOST || FUSED) {
 #pragma unroll
@@ -996,9 +1133,7 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
             key_out[p] = key;
             const bool stay = key == (uint32_t)K;
             if (stay) {
-                // column of K within row r of the block
-                const int ci = K - (bi.i0 + m.n[0] * ((bi.j0 + r % BY) + m.n[1] * (D == 3 ? bi.k0 + r / BY : 0)));
-                atomicAdd(&s_cnt[ci + BX * r], 1);
+                atomicAdd(&s_cnt[col + BX * r], 1);
             } else if (key != LOST) {
                 atomicAdd(&P.scr.n_arrive[key], 1);
             }
