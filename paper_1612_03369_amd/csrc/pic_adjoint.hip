@@ -149,11 +149,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
             double x[3], ty[4][3], k[4][3], u[3], y[3];
             int jk[4][3];
             bool near = false;
+            ijk_of<D>(m, (uint32_t)cell_in[i], jk[0]);
+            // the first stage point is the particle: its reference coordinates
+            // by the closed form, as the forward's block kernels take them
             for (int a = 0; a < D; ++a) {
                 x[a] = x_in[a * cap + i];
-                ty[0][a] = xr_in[a * cap + i];
+                ty[0][a] = (x[a] - fma((double)jk[0][a], m.h[a], m.lo[a])) * m.inv_h[a];
             }
-            ijk_of<D>(m, (uint32_t)cell_in[i], jk[0]);
             // window node index of local node (0,0,0) of cell ijk, or -1 outside the window
             auto wbase = [&](const int *ijk) {
                 const int di = ijk[0] - b0[0] + 1, dj = ijk[1] - b0[1] + 1, dk = ijk[2] - b0[2] + 1;

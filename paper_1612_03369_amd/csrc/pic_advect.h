@@ -1092,15 +1092,15 @@ __global__ __launch_bounds__(ADV_BLOCK) __attribute__((amdgpu_waves_per_eu(ODE ?
             } else {
                 key = advect_one_blk<D, S>(m, ev, dt, x, t, ijk, near);
             }
+            // The new position and key are stored; the reference coordinates
+            // and the cell array are not: until the re-sort's gather writes
+            // them (the cell from the key, the reference coordinates by the
+            // closed form), no kernel of the step sequence reads either.
             if (key != LOST || FUSED) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    out.x[a * cap + p] = x[a];
-                    out.xr[a * cap + p] = t[a];
-                }
+                for (int a = 0; a < D; ++a) out.x[a * cap + p] = x[a];
             }
             if constexpr (FUSED) {
-                out.cell[p] = K;
                 if constexpr (PIC_BLK_EARLY) {
                     out.id[p] = idv;
 #pragma unroll

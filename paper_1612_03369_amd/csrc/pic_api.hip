@@ -378,14 +378,6 @@ pic_status set_dt(pic_ctx *c, double dt)
     return PIC_OK;
 }
 
-#ifndef PIC_PLACE_WAVES
-#define PIC_PLACE_WAVES 1           // 1: wavefront placement (k_place_waves), 0: workgroup scans (k_place)
-#endif
-#if PIC_PLACE_WAVES
-#define PIC_PLACE_KERNEL k_place_waves
-#else
-#define PIC_PLACE_KERNEL k_place
-#endif
 // scan (mode 0: stayers + arrivals, 1: population packed, 2: n_arrive only)
 pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode)
 {
@@ -403,7 +395,7 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
     if (unsorted)
         LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     else
-        LAUNCH(c, "place", PIC_PLACE_KERNEL, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
     LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
     LAUNCH(c, "gather", k_gather, (unsigned)xcd_span(c->n_rp), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, count_step);
@@ -427,7 +419,7 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0);
         if (s) return s;
-        LAUNCH(c, "place", PIC_PLACE_KERNEL, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
         LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
         LAUNCH(c, "gather_advect", ff, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
         LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, 1);

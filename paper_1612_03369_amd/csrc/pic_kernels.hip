@@ -121,82 +121,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
 // place / fix / gather: the stable re-sort by (new cell, moved)
 // ===========================================================================
 /*
- * Destination of every particle of a tile of cells.  Stayers go to
- * new_start[K] + (rank among the cell's stayers): a workgroup prefix scan of
- * stay flags in store order, minus the scan value at the cell's first
- * particle.  Arrivals get a provisional slot after the destination cell's
- * stayers from an atomic cursor (each cell's first arrival slot, set by the
- * scan); k_fix orders them afterwards.
- */
-__global__ __launch_bounds__(BLOCK) void k_place(const ProblemDev *__restrict__ probs, const WorkItem *__restrict__ work,
-                                                 int n_work)
-{
-    __shared__ int s_cs[MAX_TILE + 1];
-    __shared__ int s_ncs[MAX_TILE];
-    __shared__ int s_base[MAX_TILE];
-    __shared__ int s_wave[BLOCK / 64];
-    for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
-        const int w = xcd_item(wb, n_work);
-        if (w >= n_work) continue;
-        const WorkItem wi = work[w];
-        const ProblemDev &P = probs[wi.problem];
-        const StoreDev cur = P.store[P.cur];
-        const StoreDev nxt = P.store[1 - P.cur];
-        const uint32_t *keys = P.scr.key[P.cur];
-        const int c0 = wi.c0, nt = wi.c1 - wi.c0;
-        for (int k = threadIdx.x; k <= nt; k += BLOCK) {
-            s_cs[k] = cur.cs[c0 + k];
-            if (k < nt) s_ncs[k] = nxt.cs[c0 + k];
-        }
-        __syncthreads();
-        const int p0 = s_cs[0], p1 = s_cs[nt];
-        // the key and cell of the next round are loaded while this round is placed
-        uint32_t key_n = LOST;
-        int K_n = c0;
-        if (p0 + (int)threadIdx.x < p1) {
-            key_n = keys[p0 + threadIdx.x];
-            K_n = cur.cell[p0 + threadIdx.x];
-        }
-        // The rounds synchronise through LDS only (the src writes are read by
-        // later kernels), and an arrival takes its slot at the start of the
-        // round, so that the atomic's round trip overlaps the round's scan.
-        int carry = 0;
-        for (int base = p0; base < p1; base += BLOCK) {
-            const int i = base + threadIdx.x;
-            const bool active = i < p1;
-            const uint32_t key = key_n;
-            const int K = K_n;
-            const int stay = active && key == (uint32_t)K;
-            int32_t slot;                    // set (and read) for arrivals only
-            if (active && key != LOST && !stay) slot = atomicAdd(&P.scr.cursor[key], 1);
-            if (i + BLOCK < p1) {
-                key_n = keys[i + BLOCK];
-                K_n = cur.cell[i + BLOCK];
-            }
-            int total;
-            const int pre = block_scan_flags(stay, s_wave, total);
-            const int Pi = carry + pre;
-            const int kloc = K - c0;
-            if (active && i == s_cs[kloc]) s_base[kloc] = Pi;
-            lds_barrier();
-            if (active && key != LOST) {
-                const int32_t dst = stay ? s_ncs[kloc] + (Pi - s_base[kloc]) : slot;
-                P.scr.src[dst] = i;
-            }
-            carry += total;
-            lds_barrier();
-        }
-    }
-}
-
-/*
- * The same destinations computed by each wavefront on its own, with no
- * workgroup barrier: a wave takes a run of up to 16 consecutive cells of the
- * tile (their particles are consecutive), locates each particle's cell from
- * the run's cell starts, and ranks the stayers of the run with a ballot per
- * 64 particles (the stayers of a cell are the run's stayers minus those of
- * its earlier cells, whose counts are known).  Arrivals take their slot from
- * the destination cell's atomic cursor as above.
+ * Destination of every particle of a tile of cells, each wavefront on its
+ * own with no workgroup barrier.  Stayers go to new_start[K] + (rank among
+ * the cell's stayers); arrivals get a provisional slot after the destination
+ * cell's stayers from an atomic cursor (each cell's first arrival slot, set by
+ * the scan), and k_fix orders them afterwards.  A wave takes a run of up to 16
+ * consecutive cells of the tile (their particles are consecutive), locates
+ * each particle's cell from the run's cell starts, and ranks the stayers of
+ * the run with a ballot per 64 particles (the stayers of a cell are the run's
+ * stayers minus those of its earlier cells, whose counts are known).
  */
 constexpr int PLACE_RUN = 16;
 __global__ __launch_bounds__(BLOCK) void k_place_waves(const ProblemDev *__restrict__ probs,
@@ -456,12 +389,25 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const ProblemDev *__restrict__
         const int64_t cap = P.cap;
         const int64_t s = P.scr.src[p];
         const int D = P.mesh.dim;
-        for (int a = 0; a < D; ++a) {
-            nxt.x[a * cap + p] = cur.x[a * cap + s];
-            nxt.xr[a * cap + p] = cur.xr[a * cap + s];
+        const uint32_t K = P.scr.key[P.cur][s];
+        if (P.mesh.kind == MESH_UNIFORM) {
+            // reference coordinates by the closed form that located the
+            // particle (the uniform-mesh advect kernels do not store them)
+            int ijk[3];
+            cell_ijk(P.mesh, K, ijk);
+            for (int a = 0; a < D; ++a) {
+                const double x = cur.x[a * cap + s];
+                nxt.x[a * cap + p] = x;
+                nxt.xr[a * cap + p] = (x - fma((double)ijk[a], P.mesh.h[a], P.mesh.lo[a])) * P.mesh.inv_h[a];
+            }
+        } else {
+            for (int a = 0; a < D; ++a) {
+                nxt.x[a * cap + p] = cur.x[a * cap + s];
+                nxt.xr[a * cap + p] = cur.xr[a * cap + s];
+            }
         }
         nxt.id[p] = cur.id[s];
-        nxt.cell[p] = (int32_t)P.scr.key[P.cur][s];
+        nxt.cell[p] = (int32_t)K;
         if (P.prop_f64) {
             const double *ps = (const double *)cur.prop;
             double *pd = (double *)nxt.prop;
