@@ -173,14 +173,22 @@ def measured_traffic(path=TRAFFIC_FILE):
 
 
 def bytes_per_particle(kernel, dim=3, prop_bytes=12):
+    """Bytes a kernel must move per particle as built for uniform meshes: the reference coordinates and the cell
+    are derived from the position and the block row (not read), and only the final gather stores them."""
     x = 8 * dim
     return {
-        "advect": (x + x + 4) + (x + x + 4),                            # r: x, xr, cell; w: x, xr, key
-        "place": 4 + 4 + 4,                                             # r: key, cell; w: src
+        "advect": x + (x + 4),                                          # r: x; w: x, key
+        "place": 4 + 4,                                                 # r: key; w: src
         "fix": 0,
-        "gather": (4 + 4 + x + x + 4 + prop_bytes) + (x + x + 4 + 4 + prop_bytes),
-        "gather_advect": (4 + 4 + x + x + 4 + prop_bytes) + (x + x + 4 + prop_bytes + 4 + 4),
+        "gather": (4 + 4 + x + 4 + prop_bytes) + (x + x + 4 + 4 + prop_bytes),  # r: src, key, x, id, props
+        "gather_advect": (4 + x + 4 + prop_bytes) + (x + 4 + prop_bytes + 4),   # r: src, x, id, props; w: + key
     }[kernel]
+
+
+# The same per particle-step in the paper-faithful layout (x and x-hat stored and read every step, one scatter
+# pass over the whole state): 48 + 48 + 4 written by the advect, 4 + 64 + 64 by the scatter, the key read, about
+# 5 B of field and 0.4 B of counts per particle at 64^3 -- about 237 B, the model the 64^3 gate is priced on.
+PAPER_STEP_BYTES = 237.0
 
 
 KERNELS = ("advect", "gather_advect", "scan_reduce", "scan_down", "place", "fix", "gather", "flip")
@@ -269,6 +277,8 @@ def run_main(args):
                      "traffic_source": traffic_src, "bytes_per_launch": bytes_launch,
                      "avg_launch_us": kernels[dom]["avg_us"]},
         "step_hbm_frac": step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_bytes_per_particle": step_bytes / avg_particles,
+        "step_hbm_frac_paper_model": avg_particles * PAPER_STEP_BYTES / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
         "stats": st,
     }
