@@ -359,15 +359,15 @@ def bench_adjoint(args):
 
     both = timed(fwd_bwd)
     # the reverse-step kernel alone: its mean launch time from the library's HIP events, priced at the bytes it
-    # must move (per particle-step: x, x-hat, cell, dst and lambda' read, lambda written; per launch: the field
-    # window's nodes and dU read and written once)
+    # must move (per particle-step: x, cell, dst and lambda' read, lambda written -- the first stage point's
+    # reference coordinates come from x and the cell; per launch: the field's nodes and dU read and written once)
     p.seed_reference(cfg["counts"], cfg["xr"], cfg["ids"])
     p.profile(True)
     fwd_bwd()
     torch.cuda.synchronize()
     ms, cnt = p.profile_read("adjoint_step")
     p.profile(False)
-    per_particle = 8 * 3 + 8 * 3 + 4 + 4 + 8 * 3 + 8 * 3
+    per_particle = 8 * 3 + 4 + 4 + 8 * 3 + 8 * 3
     per_node = 32 + 2 * 8 * 3
     bytes_launch = n0 * per_particle + mesh.n_nodes * per_node
     avg_us = 1e3 * ms / max(cnt, 1)
