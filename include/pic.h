@@ -297,6 +297,18 @@ PIC_API pic_status pic_set_property_odes(pic_ctx *ctx, int32_t damage_prop, int3
  * keep their order and arrivals follow in their previous order.  eval_prec
  * selects the arithmetic of the field evaluation (locations stay double). */
 PIC_API pic_status pic_advance(pic_ctx *ctx, double dt, int32_t n_steps, int32_t scheme, int32_t eval_prec);
+/* Several steps on a uniform mesh run as one launch sequence (the re-sort of
+ * each step fused with the next step's advection).  With enable = 1,
+ * pic_advance records that sequence once into a HIP graph on a stream of the
+ * context's own and replays it, after the work already on the context's stream
+ * and before the work put there later (one event each way); a new step count,
+ * scheme, precision or property-equation / time-field setting records a new
+ * graph, and so do new work lists (binding, tile size, mesh).  enable = 0 (the
+ * default) launches the kernels one by one on the context's stream, which
+ * measured faster (50 steps of the 64^3 RK4 workload: 15.7-15.9 ms against
+ * 16.4-16.7 ms from the graph).  The results are the same bit for bit.
+ * Profiling (pic_profile_enable) always launches one by one. */
+PIC_API pic_status pic_set_launch_graphs(pic_ctx *ctx, int32_t enable);
 
 /* ---- population management (Sec. 2.5, Sec. 2.6) ----------------------- */
 /* Per cell: more than max_pc particles -> delete the ones with the largest

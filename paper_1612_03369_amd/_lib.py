@@ -31,7 +31,7 @@ EXPORTS = [
     "pic_set_velocity", "pic_set_velocity_end", "pic_shift_velocity", "pic_set_field_time", "pic_field_time",
     "pic_scratch_bytes", "pic_bind_store", "pic_current_buffer", "pic_set_tile",
     "pic_seed_reference", "pic_seed_per_cell", "pic_seed_positions", "pic_set_property_odes", "pic_advance", "pic_population",
-    "pic_interpolate", "pic_interpolate_points", "pic_seed_mh", "pic_seed_mh_static", "pic_transfer",
+    "pic_interpolate", "pic_interpolate_points", "pic_seed_mh", "pic_seed_mh_static", "pic_transfer", "pic_set_launch_graphs",
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
     "pic_batch_create", "pic_batch_advance", "pic_batch_set_schedule", "pic_batch_tune", "pic_batch_destroy",
@@ -101,6 +101,7 @@ def load(path: str | None = None):
             "pic_interpolate_points": (S, [P, I32, P, I32, P, P]),
             "pic_seed_mh": (S, [P, P, P, I32, C.c_uint64, C.c_uint32, P]),
             "pic_seed_mh_static": (S, [P, P, P, I32, C.c_uint64, C.c_uint32, P]),
+            "pic_set_launch_graphs": (S, [P, I32]),
             "pic_transfer": (S, [P, P]),
             "pic_shift_velocity": (S, [P, P, I32, C.c_double]),
             "pic_set_field_time": (S, [P, C.c_double]),

@@ -349,6 +349,11 @@ class Problem:
     def stats_reset(self):
         self._chk(self.lib.pic_stats_reset(self.h))
 
+    def set_launch_graphs(self, enable: bool):
+        """Replay the fused step sequence of advance() from a captured HIP graph, or launch its kernels one by
+        one (the default, measured faster)."""
+        self._chk(self.lib.pic_set_launch_graphs(self.h, int(bool(enable))))
+
     def profile(self, enable: bool):
         self._chk(self.lib.pic_profile_enable(self.h, int(bool(enable))))
 

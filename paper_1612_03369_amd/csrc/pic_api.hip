@@ -91,6 +91,16 @@ struct pic_ctx {
     std::vector<ProfEvent> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> prof;
+    // graph of the fused step sequence of pic_advance, captured on a stream of
+    // the context's own (the caller's may be the legacy default stream, which
+    // cannot be captured) and replayed between events on the two streams;
+    // key = {n_steps, scheme, precision, property equations, time field}
+    bool graphs = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t g_ev[2] = {nullptr, nullptr};
+    hipGraph_t g_graph = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    int g_key[5] = {-1, -1, -1, -1, -1};
     // adjoint
     int64_t adj_steps = 0, adj_every = 0;
     double adj_dt = 0.0;
@@ -193,8 +203,10 @@ template <typename T> pic_status mesh_upload(pic_ctx *c, const T *host, size_t n
     return PIC_OK;
 }
 
+void drop_adv_graph(pic_ctx *c);
 void free_mesh(pic_ctx *c)
 {
+    drop_adv_graph(c);
     for (void *p : c->mesh_allocs) hipFree(p);
     c->mesh_allocs.clear();
     if (c->u64) hipFree(c->u64);
@@ -301,9 +313,19 @@ std::vector<BlockItem> block_items(const MeshDev &m, int prec, int problem)
     return v;
 }
 
-// Work lists for one problem.
+void drop_adv_graph(pic_ctx *c)
+{
+    if (c->g_exec) hipGraphExecDestroy(c->g_exec);
+    if (c->g_graph) hipGraphDestroy(c->g_graph);
+    c->g_exec = nullptr;
+    c->g_graph = nullptr;
+    for (int &k : c->g_key) k = -1;
+}
+
+// Work lists for one problem (a captured step sequence holds their pointers).
 pic_status build_work(pic_ctx *c)
 {
+    drop_adv_graph(c);
     const int64_t nc = c->mesh.n_cells;
     const int64_t cap = c->store.capacity;
     std::vector<WorkItem> w;
@@ -481,6 +503,11 @@ extern "C" void pic_destroy(pic_ctx *c)
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
+    if (c->gstream) hipStreamSynchronize(c->gstream);
+    drop_adv_graph(c);
+    if (c->gstream) hipStreamDestroy(c->gstream);
+    for (hipEvent_t e : c->g_ev)
+        if (e) hipEventDestroy(e);
     free_mesh(c);
     for (void *p : {c->u64, c->u32, c->u1_64, c->u1_32, (void *)c->d_tau, (void *)c->d_prob, (void *)c->d_work, (void *)c->d_scan, (void *)c->d_rp,
                     (void *)c->d_rc, (void *)c->d_blk[0], (void *)c->d_blk[1], (void *)c->d_blk_adj})
@@ -1040,6 +1067,51 @@ extern "C" pic_status pic_set_property_odes(pic_ctx *c, int32_t damage_prop, int
     return upload_problem(c);
 }
 
+namespace {
+// The fused step sequence from its captured graph (captured at the first call
+// with a new key), ordered after the caller's earlier work and before its
+// later work by one event on each stream.
+pic_status advance_graph(pic_ctx *c, int scheme, int prec, int n)
+{
+    if (!c->gstream) {
+        HIPCHK(c, hipStreamCreate(&c->gstream));
+        for (hipEvent_t &e : c->g_ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    const int key[5] = {n, scheme, prec, c->h_prob.odes ? 1 : 0, c->h_prob.ti ? 1 : 0};
+    if (!c->g_exec || !std::equal(key, key + 5, c->g_key)) {
+        drop_adv_graph(c);
+        HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        hipStream_t caller = c->stream;
+        c->stream = c->gstream;
+        pic_status s = enqueue_steps_fused(c, c->d_prob, scheme, prec, n);
+        c->stream = caller;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->gstream, &g);
+        if (s || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return s ? s : fail(c, PIC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+        c->g_graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->g_exec, g, nullptr, nullptr, 0));
+        std::copy(key, key + 5, c->g_key);
+    }
+    HIPCHK(c, hipEventRecord(c->g_ev[0], c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->gstream, c->g_ev[0], 0));
+    HIPCHK(c, hipGraphLaunch(c->g_exec, c->gstream));
+    HIPCHK(c, hipEventRecord(c->g_ev[1], c->gstream));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->g_ev[1], 0));
+    return PIC_OK;
+}
+}  // namespace
+
+extern "C" pic_status pic_set_launch_graphs(pic_ctx *c, int32_t enable)
+{
+    if (!c) return PIC_EINVAL;
+    c->graphs = enable != 0;
+    if (!c->graphs) drop_adv_graph(c);
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_advance(pic_ctx *c, double dt, int32_t n_steps, int32_t scheme, int32_t eval_prec)
 {
     pic_status s = require_ready(c, true);
@@ -1051,8 +1123,10 @@ extern "C" pic_status pic_advance(pic_ctx *c, double dt, int32_t n_steps, int32_
     if (c->mesh.kind == MESH_OCTREE && c->mesh.dim != 3) return fail(c, PIC_EINVAL, "octree is 3D");
     hipSetDevice(c->device);
     if ((s = set_dt(c, dt))) return s;
-    if (PIC_FUSE_STEPS && PIC_USE_BLOCK_ADVECT && n_steps > 1 && c->mesh.kind == MESH_UNIFORM && c->n_blk[eval_prec == PIC_F32])
+    if (PIC_FUSE_STEPS && PIC_USE_BLOCK_ADVECT && n_steps > 1 && c->mesh.kind == MESH_UNIFORM && c->n_blk[eval_prec == PIC_F32]) {
+        if (c->graphs && !c->profile) return advance_graph(c, scheme, eval_prec, n_steps);
         return enqueue_steps_fused(c, c->d_prob, scheme, eval_prec, n_steps);
+    }
     for (int k = 0; k < n_steps; ++k)
         if ((s = enqueue_step(c, c->d_prob, scheme, eval_prec))) return s;
     return PIC_OK;
