@@ -70,6 +70,9 @@ __device__ __forceinline__ void grad_basis_at(Ptr U, I base, I sy, I sz, const d
             }
 }
 
+// v[k] for k in {0, 1, 2} by selects (no run-time indexing of a register array)
+__device__ __forceinline__ double sel3(const double *v, int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
+
 /*
  * One reverse step on a uniform mesh.  Work item = block of cells of the
  * step's input state (its particles are runs of consecutive cells); dst[i] is
@@ -98,6 +101,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     const double dt = P.dt;
     auto Ug = (gptr<V>)P.u64;
     const int64_t nn = m.n_nodes;
+    // the lane's digit offsets of the dU walk (see below): rotated local
+    // indices along each axis and the window offsets of the (b, c) rows
+    int rot_a[3], rot_b[3], rot_c[3], off_bc[3][3];
+    {
+        const int rot = (threadIdx.x & 63) % (D == 3 ? 27 : 9);
+        const int oa = rot % 3, ob = (rot / 3) % 3, oc = D == 3 ? rot / 9 : 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            rot_a[i] = (i + oa) % 3;
+            rot_b[i] = (i + ob) % 3;
+            rot_c[i] = (i + oc) % 3;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) off_bc[i][j] = Wn::WX * (rot_b[i] + (D == 3 ? Wn::WY * rot_c[j] : 0));
+    }
     for (int wb = blockIdx.x; wb < xcd_span(n_work); wb += gridDim.x) {
         const int w = xcd_item(wb, n_work);
         if (w >= n_work) continue;
@@ -216,10 +236,40 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
                 if constexpr (D == 3) inw &= (unsigned)dk < (unsigned)(BZ + 2);
                 // Lanes holding particles of one cell would add to the same
                 // node at the same time (serialised LDS atomics); each lane
-                // starts its walk over the cell's nodes at its own offset.
+                // walks the cell's nodes from its own start: step (ra, rb, rc)
+                // visits node ((ra + oa) mod 3, (rb + ob) mod 3, (rc + oc) mod 3)
+                // with the lane's digit offsets, so lanes with different
+                // offsets never meet.  The rotated basis values, node offsets
+                // and weights are formed once per stage; the walk is unrolled.
                 constexpr int NB = D == 3 ? 27 : 9;
+                if (inw) {
+                    const int base = 2 * di + Wn::WX * (2 * dj + (D == 3 ? Wn::WY * 2 * dk : 0));
+                    double LA[3], LBC[3][3], dk3[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        LA[i] = sel3(l[0], rot_a[i]);
+                        const double lbi = sel3(l[1], rot_b[i]);
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) LBC[i][j] = D == 3 ? lbi * sel3(l[2], rot_c[j]) : (j == 0 ? lbi : 0.0);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) dk3[c] = c < D ? dt * kb[st][c] : 0.0;
+#pragma unroll
+                    for (int rc = 0; rc < (D == 3 ? 3 : 1); ++rc)
+#pragma unroll
+                        for (int rb = 0; rb < 3; ++rb) {
+                            const int qbc = base + off_bc[rb][rc];
+#pragma unroll
+                            for (int ra = 0; ra < 3; ++ra) {
+                                const double ph = LA[ra] * LBC[rb][rc];
+                                const int q = qbc + rot_a[ra];
+#pragma unroll
+                                for (int c = 0; c < D; ++c) atomicAdd(&s_acc[c * Wn::NODES + q], ph * dk3[c]);
+                            }
+                        }
+                }
                 const int rot = (threadIdx.x & 63) % NB;
-                for (int r = 0; r < NB; ++r) {
+                for (int r = 0; r < NB && !inw; ++r) {
                     const int nq = r + rot >= NB ? r + rot - NB : r + rot;
                     const int a = nq % 3, b = (nq / 3) % 3, c3 = D == 3 ? nq / 9 : 0;
                     const double la = a == 0 ? l[0][0] : (a == 1 ? l[0][1] : l[0][2]);
@@ -227,10 +277,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
                     double ph = la * lb;
                     if constexpr (D == 3) ph *= c3 == 0 ? l[2][0] : (c3 == 1 ? l[2][1] : l[2][2]);
                     const double f = dt * ph;
-                    if (inw) {
-                        const int q = (2 * di + a) + Wn::WX * ((2 * dj + b) + Wn::WY * (D == 3 ? 2 * dk + c3 : 0));
-                        for (int c = 0; c < D; ++c) atomicAdd(&s_acc[c * Wn::NODES + q], f * kb[st][c]);
-                    } else {
+                    {
                         const int64_t g = (2 * jk[st][0] + a) + (int64_t)m.nnx * ((2 * jk[st][1] + b) +
                                           (int64_t)m.nny * (D == 3 ? 2 * jk[st][2] + c3 : 0));
                         for (int c = 0; c < D; ++c) unsafeAtomicAdd(&dU[c * nn + g], f * kb[st][c]);
