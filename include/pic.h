@@ -405,6 +405,19 @@ PIC_API pic_status pic_batch_set_schedule(pic_batch *b, const int32_t variant[6]
  * pic_batch_advance.  Needs device memory for one copy of the locations. */
 PIC_API pic_status pic_batch_tune(pic_batch *b, const double *dt, const int32_t *scheme, int32_t trials,
                                   int32_t variant_out[6], double time_ms_out[18]);
+/* Tune cache: the batch's schedule as text, for reuse without timing.
+ * pic_batch_tune_cache_write writes
+ *   {"signature": [[dim, n_cells, capacity, scheme], ...], "variants": [v0, .. v5]}
+ * (one signature entry per problem, with the schemes given) into buf (host,
+ * cap bytes, NUL-terminated); *len receives the length without the NUL, so
+ * cap = 0 asks for the length alone; a smaller nonzero cap -> PIC_EINVAL.
+ * pic_batch_tune_cache_apply reads that text: when its signature equals the
+ * batch's (for the schemes given) it applies the variants as
+ * pic_batch_set_schedule does and sets *applied = 1, else it changes nothing
+ * and sets *applied = 0.  Malformed text or variants outside 0..2 ->
+ * PIC_EINVAL. */
+PIC_API pic_status pic_batch_tune_cache_write(pic_batch *b, const int32_t *scheme, char *buf, int64_t cap, int64_t *len);
+PIC_API pic_status pic_batch_tune_cache_apply(pic_batch *b, const int32_t *scheme, const char *json, int32_t *applied);
 PIC_API void pic_batch_destroy(pic_batch *b);
 PIC_API const char *pic_batch_last_error(const pic_batch *b);
 

@@ -35,6 +35,7 @@ EXPORTS = [
     "pic_adjoint_workspace_bytes", "pic_advance_checkpointed", "pic_adjoint",
     "pic_stats_read", "pic_stats_reset", "pic_profile_enable", "pic_profile_read",
     "pic_batch_create", "pic_batch_advance", "pic_batch_set_schedule", "pic_batch_tune", "pic_batch_destroy",
+    "pic_batch_tune_cache_write", "pic_batch_tune_cache_apply",
     "pic_batch_last_error",
 ]
 
@@ -119,6 +120,8 @@ def load(path: str | None = None):
             "pic_batch_advance": (S, [P, P, P, I32]),
             "pic_batch_set_schedule": (S, [P, P]),
             "pic_batch_tune": (S, [P, P, P, I32, P, P]),
+            "pic_batch_tune_cache_write": (S, [P, P, C.c_char_p, C.c_int64, P]),
+            "pic_batch_tune_cache_apply": (S, [P, P, C.c_char_p, P]),
             "pic_batch_destroy": (None, [P]),
             "pic_batch_last_error": (C.c_char_p, [P]),
         }

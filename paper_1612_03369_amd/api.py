@@ -398,22 +398,36 @@ class Batch:
         v = (C.c_int32 * 6)(*[int(x) for x in variants])
         L.check(self.lib.pic_batch_set_schedule(self.h, v), batch=self.h)
 
-    def signature(self, schemes):
-        """What the schedule depends on: per problem dim, cells, capacity and scheme."""
-        return [[p.dim, int(p.n_cells), int(p.store.capacity), int(s)] for p, s in zip(self.problems, schemes)]
+    def tune_cache(self, schemes):
+        """The library's tune-cache text of the current schedule for these schemes."""
+        n = len(self.problems)
+        sc = (C.c_int32 * n)(*[int(v) for v in schemes])
+        ln = C.c_int64()
+        L.check(self.lib.pic_batch_tune_cache_write(self.h, sc, None, 0, C.byref(ln)), batch=self.h)
+        buf = C.create_string_buffer(ln.value + 1)
+        L.check(self.lib.pic_batch_tune_cache_write(self.h, sc, buf, ln.value + 1, C.byref(ln)), batch=self.h)
+        return buf.value.decode()
+
+    def apply_tune_cache(self, schemes, text):
+        """Apply a tune-cache text when its signature matches these problems and schemes; True if applied."""
+        n = len(self.problems)
+        sc = (C.c_int32 * n)(*[int(v) for v in schemes])
+        ok = C.c_int32()
+        L.check(self.lib.pic_batch_tune_cache_apply(self.h, sc, text.encode(), C.byref(ok)), batch=self.h)
+        return bool(ok.value)
 
     def tune(self, dts, schemes, trials=3, cache=None):
         """Pick the fastest cell-block shape per group (the library's autotuner) and return
-        {"variants": [...], "times_ms": {...}}.  With `cache` (a JSON path) a stored choice for the
-        same signature is applied without timing, and a new choice is stored."""
+        {"variants": [...], "times_ms": {...}}.  With `cache` (a file path) the library's tune-cache text
+        stored there is applied without timing when its signature matches, and a new choice is stored."""
         import json
         import os
-        sig = self.signature(schemes)
         if cache and os.path.exists(cache):
             with open(cache) as f:
-                rec = json.load(f)
-            if rec.get("signature") == sig:
-                self.set_schedule(rec["variants"])
+                text = f.read()
+            if self.apply_tune_cache(schemes, text):
+                rec = json.loads(text)
+                rec["cached"] = True
                 return rec
         n = len(self.problems)
         dt = (C.c_double * n)(*[float(v) for v in dts])
@@ -430,10 +444,11 @@ class Batch:
             if tms[3 * g] >= 0:
                 d = 2 if g < 3 else 3
                 times[name] = {"x".join(map(str, self.SHAPES[d][v])): tms[3 * g + v] for v in range(3)}
-        rec = {"signature": sig, "variants": list(var), "times_ms": times}
+        rec = json.loads(self.tune_cache(schemes))
+        rec["times_ms"] = times
         if cache:
             with open(cache, "w") as f:
-                json.dump(rec, f)
+                f.write(self.tune_cache(schemes))
         return rec
 
     def close(self):

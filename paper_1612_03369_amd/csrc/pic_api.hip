@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cerrno>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>

@@ -395,3 +395,42 @@ def test_seed_positions_matches_oracle_locate(L):
     assert np.array_equal(g["x"], x[:, g["id"]])
     assert p.stats()["lost"] == 3000 - len(exp)
     p.close()
+
+
+def test_batch_tune_cache(L, tmp_path):
+    """The library's tune cache: the text written for a batch applies to the same problems and schemes,
+    changes nothing for other schemes, rejects malformed text and out-of-range shapes; tune(cache=...)
+    stores a choice and reuses it without timing."""
+    import json
+    from paper_1612_03369_amd._lib import PicError
+    from paper_1612_03369_amd.api import Batch
+    _say("case: batch tune cache")
+    cfgs = [_fourier_cfg(2, 16, 6, seed=220), _fourier_cfg(3, 8, 6, seed=221), _fourier_cfg(3, 8, 6, seed=222)]
+    probs = [gpu_problem(c) for c in cfgs]
+    b = Batch(probs)
+    schemes = [2, 4, 4]
+    text = b.tune_cache(schemes)
+    rec = json.loads(text)
+    assert rec["variants"] == [0] * 6
+    assert rec["signature"] == [[c["mesh"].dim, c["mesh"].n_cells, c["xr"].shape[1], s] for c, s in zip(cfgs, schemes)]
+    rec["variants"] = [1, 2, 1, 0, 2, 1]
+    assert b.apply_tune_cache(schemes, json.dumps(rec))
+    assert json.loads(b.tune_cache(schemes))["variants"] == [1, 2, 1, 0, 2, 1]
+    assert not b.apply_tune_cache([2, 2, 4], json.dumps(dict(rec, variants=[0] * 6)))   # other schemes
+    assert json.loads(b.tune_cache(schemes))["variants"] == [1, 2, 1, 0, 2, 1]
+    for bad in ("", "{}", text[:-1], text + "x", json.dumps(dict(rec, variants=[0, 0, 0, 0, 0, 3])),
+                json.dumps(dict(rec, variants=[0, 0, 0]))):
+        with pytest.raises(PicError) as e:
+            b.apply_tune_cache(schemes, bad)
+        assert e.value.status == L.PIC_EINVAL
+    path = str(tmp_path / "tune.json")
+    dts = [0.5 / c["mesh"].n[0] for c in cfgs]
+    first = b.tune(dts, schemes, trials=1, cache=path)
+    assert "times_ms" in first and not first.get("cached")
+    b.set_schedule([2] * 6)
+    again = b.tune(dts, schemes, trials=1, cache=path)
+    assert again.get("cached") and again["variants"] == first["variants"]
+    assert json.loads(b.tune_cache(schemes))["variants"] == first["variants"]
+    b.close()
+    for p in probs:
+        p.close()
