@@ -37,37 +37,80 @@ template <int D, typename Ptr, typename I>
 __device__ __forceinline__ void grad_basis_at(Ptr U, I base, I sy, I sz, const double *t, double Gr[3][3],
                                               double l[3][3])
 {
+    // sum-factorised: along x the value and derivative sums of each node row,
+    // then along y, then along z (value sums carry the other axes' weights)
     double dl[3][3];
     for (int a = 0; a < D; ++a) {
         lag3(t[a], l[a]);
         dlag3(t[a], dl[a]);
     }
-    for (int c = 0; c < 3; ++c)
-        for (int r = 0; r < 3; ++r) Gr[c][r] = 0.0;
-#pragma unroll 1
-    for (int c3 = 0; c3 < (D == 3 ? 3 : 1); ++c3)
+    if constexpr (D == 2) {
+        double sx[2] = {0, 0}, sy_[2] = {0, 0};
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < 3; ++b) {
+            double r0[2] = {0, 0}, rd[2] = {0, 0};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const auto v = U[base + a + sy * b + sz * c3];
-                double w0, w1, w2 = 0.0;
-                if constexpr (D == 2) {
-                    w0 = dl[0][a] * l[1][b];
-                    w1 = l[0][a] * dl[1][b];
-                } else {
-                    w0 = dl[0][a] * l[1][b] * l[2][c3];
-                    w1 = l[0][a] * dl[1][b] * l[2][c3];
-                    w2 = l[0][a] * l[1][b] * dl[2][c3];
-                }
-                const double vc[3] = {(double)nv_x(v), (double)nv_y(v), (double)nv_z(v)};
+                const auto v = U[base + a + sy * b];
+                const double vc[2] = {(double)nv_x(v), (double)nv_y(v)};
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    Gr[c][0] = fma(vc[c], w0, Gr[c][0]);
-                    Gr[c][1] = fma(vc[c], w1, Gr[c][1]);
-                    if constexpr (D == 3) Gr[c][2] = fma(vc[c], w2, Gr[c][2]);
+                for (int c = 0; c < 2; ++c) {
+                    r0[c] = fma(vc[c], l[0][a], r0[c]);
+                    rd[c] = fma(vc[c], dl[0][a], rd[c]);
                 }
             }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                sx[c] = fma(rd[c], l[1][b], sx[c]);
+                sy_[c] = fma(r0[c], dl[1][b], sy_[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Gr[c][0] = Gr[c][1] = Gr[c][2] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            Gr[c][0] = sx[c];
+            Gr[c][1] = sy_[c];
+        }
+    } else {
+        double gx[3] = {0, 0, 0}, gy[3] = {0, 0, 0}, gz[3] = {0, 0, 0};
+#pragma unroll 1
+        for (int c3 = 0; c3 < 3; ++c3) {
+            double p0[3] = {0, 0, 0}, px[3] = {0, 0, 0}, py[3] = {0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                double r0[3] = {0, 0, 0}, rd[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const auto v = U[base + a + sy * b + sz * c3];
+                    const double vc[3] = {(double)nv_x(v), (double)nv_y(v), (double)nv_z(v)};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        r0[c] = fma(vc[c], l[0][a], r0[c]);
+                        rd[c] = fma(vc[c], dl[0][a], rd[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    p0[c] = fma(r0[c], l[1][b], p0[c]);
+                    px[c] = fma(rd[c], l[1][b], px[c]);
+                    py[c] = fma(r0[c], dl[1][b], py[c]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                gx[c] = fma(px[c], l[2][c3], gx[c]);
+                gy[c] = fma(py[c], l[2][c3], gy[c]);
+                gz[c] = fma(p0[c], dl[2][c3], gz[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Gr[c][0] = gx[c];
+            Gr[c][1] = gy[c];
+            Gr[c][2] = gz[c];
+        }
+    }
 }
 
 // v[k] for k in {0, 1, 2} by selects (no run-time indexing of a register array)

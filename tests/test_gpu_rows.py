@@ -176,22 +176,23 @@ def test_batch_bit_identical_to_single_runs(L, schedule):
 
 
 # ----------------------------------------------------------------------------
-def _adjoint_case(L, n=6, ppc=3, steps=8, scheme=4, ckpt=3, seed=301):
-    mesh = I.UniformMesh(3, (n, n, n))
+def _adjoint_case(L, n=6, ppc=3, steps=8, scheme=4, ckpt=3, seed=301, dim=3):
+    mesh = I.UniformMesh(dim, (n,) * dim)
     nodes = I.uniform_q2_nodes(mesh)
-    U = I.normalise_nodal(I.sample_nodes(I.FourierField(3, seed=seed, tangential=True).velocity, nodes))
+    U = I.normalise_nodal(I.sample_nodes(I.FourierField(dim, seed=seed, tangential=True).velocity, nodes))
     counts = np.full(mesh.n_cells, ppc, np.int32)
-    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=seed + 1)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=seed + 1)
     cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=0, prop_dtype=np.float64)
     return cfg, 0.5 / n, steps, scheme, ckpt
 
 
+@pytest.mark.parametrize("dim", [3, 2])
 @pytest.mark.parametrize("scheme", [2, 4])
-def test_adjoint_matches_oracle_gradient(L, scheme):
-    _say(f"case: adjoint vs oracle, scheme {scheme}")
+def test_adjoint_matches_oracle_gradient(L, scheme, dim):
+    _say(f"case: adjoint vs oracle, {dim}D, scheme {scheme}")
     import torch
     from paper_1612_03369_amd.adjoint import ParticleFlow, advect
-    cfg, dt, steps, _, ckpt = _adjoint_case(L, scheme=scheme)
+    cfg, dt, steps, _, ckpt = _adjoint_case(L, scheme=scheme, dim=dim, **({} if dim == 3 else dict(n=10, ppc=4)))
     p = gpu_problem(cfg)
     flow = ParticleFlow(p, cfg["counts"], cfg["xr"], cfg["ids"], dt, steps, scheme, ckpt)
     U = torch.tensor(cfg["U"], dtype=torch.float64, device=p.device, requires_grad=True)
@@ -203,7 +204,7 @@ def test_adjoint_matches_oracle_gradient(L, scheme):
     O.run(om, cfg["U"], dt, scheme, steps, fin)
     f = fin.view()
     n_id = xT.shape[1]
-    x_or = np.full((3, n_id), np.nan)
+    x_or = np.full((dim, n_id), np.nan)
     x_or[:, f["id"]] = f["x"]
     rng = np.random.default_rng(7)
     tgt_np = x_or + 0.01 * rng.standard_normal(x_or.shape)
