@@ -275,6 +275,9 @@ def run_main(args):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic if dom == "gather_advect" else None,
                      "traffic_source": traffic_src, "bytes_per_launch": bytes_launch,
+                     "bytes_per_particle": bytes_per_particle(dom),
+                     "bytes_model": "as built: x-hat and cell derived from x and the block row, stored only by the "
+                                    "final gather; plus 12 B per Q2 node of field",
                      "avg_launch_us": kernels[dom]["avg_us"]},
         "step_hbm_frac": step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_bytes_per_particle": step_bytes / avg_particles,
