@@ -215,9 +215,12 @@ def test_crowded_cell_many_arrivals(L):
     p.close()
 
 
-def test_fp32_evaluation_against_fp64_oracle(L):
-    _say("case: FP32 field evaluation, 16^3, RK4")
-    cfg = I.config2(eval_f32=True, n=16, ppc=6, steps=20)
+@pytest.mark.parametrize("n", [16, 13])
+def test_fp32_evaluation_against_fp64_oracle(L, n):
+    """16^3 and a mesh of 13^3 cells, whose cell blocks at the upper faces are ragged (the x-Horner window and
+    the cell-from-row lookup of partial blocks)."""
+    _say(f"case: FP32 field evaluation, {n}^3, RK4")
+    cfg = I.config2(eval_f32=True, n=n, ppc=6, steps=20)
     p = gpu_problem(cfg)
     p.advance(cfg["dt"], cfg["steps"], L.PIC_RK4, L.PIC_F32)
     g = p.numpy()
