@@ -1041,37 +1041,6 @@ __device__ __forceinline__ int xcd_item(int b, int n) { return (b % N_XCD) * ((n
 // ---------------------------------------------------------------------------
 // workgroup helpers
 // ---------------------------------------------------------------------------
-// Exclusive scan of 0/1 flags over a 256-thread workgroup; returns the prefix
-// and the workgroup total.  s_wave must hold BLOCK/64 ints.
-// Workgroup barrier that orders LDS accesses only: global memory operations
-// issued before it need not have completed (for kernels whose workgroups do
-// not read back their own global writes).
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-__device__ __forceinline__ int block_scan_flags(int flag, int *s_wave, int &total)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const unsigned long long m = __ballot(flag);
-    const int pre = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) s_wave[wid] = __popcll(m);
-    lds_barrier();
-    int off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < BLOCK / 64; ++w) {
-        int c = s_wave[w];
-        off += (w < wid) ? c : 0;
-        tot += c;
-    }
-    lds_barrier();
-    total = tot;
-    return off + pre;
-}
-
 // Sum of an int over a wavefront.
 __device__ __forceinline__ int wave_sum(int v)
 {
