@@ -676,16 +676,21 @@ __device__ __forceinline__ uint32_t advect_one_blk(const MeshDev &m, Eval &&ev, 
 }
 
 /*
- * Work item = block of cells of a uniform mesh.  The workgroup copies the
- * Q2 nodes of the block's cells plus a one-cell halo into LDS once, then advances every particle of the block's cells; stage points in
- * the halo read LDS, the rare ones farther away read global memory.
+ * Work item = block of cells of a uniform mesh.  The workgroup stages a window
+ * of the field over the block's cells plus a one-cell halo in LDS once (the
+ * x-Horner rows or the Q2 node lattice), then advances every particle of the
+ * block's cells; stage points in the halo read LDS, the rare ones farther away
+ * read global memory.  A particle's cell is the cell of its block row whose
+ * range holds its slot, and its reference coordinates the closed form of its
+ * position in that cell: neither is read, and neither is stored (the
+ * re-sort's gather writes both when it forms the final store).
  *
- * FUSED = false: the particles are those of the current buffer; new location,
- * reference location and key are written in place (as k_advect).
+ * FUSED = false: the particles are those of the current buffer; the new
+ * location and the key are written in place.
  * FUSED = true: the particles are the destination slots p of the re-sort in
  * progress (cells of the other buffer, whose cell_start the scan produced);
  * slot p takes particle src[p] of the current buffer, advances it by the next
- * step and writes it, its id, properties, cell and new key to the other
+ * step and writes its location, id, properties and new key to the other
  * buffer.  A fused step is thus "finish the previous step's permutation and
  * compute the next step's keys" in one pass over the particle state.
  */
