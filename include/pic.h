@@ -83,7 +83,12 @@ typedef enum { PIC_PROP_GIVEN = 0, PIC_PROP_INITIAL_POSITION = 1 } pic_prop_init
  * the other one, sorted by cell.  cell_start[b] has n_cells+1 entries; the
  * particles of cell K in buffer b are [cell_start[b][K], cell_start[b][K+1]),
  * and the live count is cell_start[b][n_cells].  All pointers are device
- * pointers owned by the caller.
+ * pointers owned by the caller.  Between calls the current buffer holds every
+ * field; the other buffer is scratch of the calls.  On uniform meshes the
+ * stored reference location of a particle is exactly the closed form
+ * (x - (lo + i h)) / h of its location in its cell, and the step kernels use
+ * that form instead of reading it (so the given reference locations of a
+ * seeding call enter the first step only through the locations they map to).
  */
 typedef struct {
     int64_t capacity;          /* particles per buffer */
