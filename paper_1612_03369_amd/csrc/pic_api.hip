@@ -403,25 +403,46 @@ pic_status set_dt(pic_ctx *c, double dt)
     return PIC_OK;
 }
 
-// scan (mode 0: stayers + arrivals, 1: population packed, 2: n_arrive only)
-pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode)
+// scan (mode 0: stayers + arrivals, 1: population packed, 2: n_arrive only);
+// flip: the buffer flip of a fused step is still pending (mode 0 only)
+pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode, bool flip = false)
 {
-    LAUNCH(c, "scan_reduce", k_scan_reduce, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
+    LAUNCH(c, "scan_reduce", k_scan_reduce, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode,
+           dp, flip ? 1 : 0);
     LAUNCH(c, "scan_down", k_scan_down, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
     return PIC_OK;
 }
 
-// place + fix + gather + flip after the counts are in n_stay / n_arrive;
-// unsorted = the current buffer is an unsorted input (every particle arrives)
-pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorted = false)
+#ifndef PIC_PLACE_GRID_MAX
+#define PIC_PLACE_GRID_MAX 0
+#endif
+unsigned place_grid(int n_work)
 {
-    pic_status s = enqueue_scan(c, dp, 0);
-    if (s) return s;
-    if (unsorted)
-        LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
-    else
-        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+    const int g = xcd_span(n_work);
+    return (unsigned)(PIC_PLACE_GRID_MAX > 0 && g > PIC_PLACE_GRID_MAX ? PIC_PLACE_GRID_MAX : g);
+}
+
+// arrival order after the placement of a buffer sorted by cell
+pic_status enqueue_fix_sorted(pic_ctx *c, ProblemDev *dp)
+{
     LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+    return PIC_OK;
+}
+
+// place + fix + gather + flip after the counts are in n_stay / n_arrive;
+// unsorted = the current buffer is an unsorted input (every particle arrives);
+// flip = a fused step's flip is pending (done by the scan)
+pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorted = false, bool flip = false)
+{
+    pic_status s = enqueue_scan(c, dp, 0, flip);
+    if (s) return s;
+    if (unsorted) {
+        LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
+        LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+    } else {
+        LAUNCH(c, "place", k_place_waves, place_grid(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        if ((s = enqueue_fix_sorted(c, dp))) return s;
+    }
     LAUNCH(c, "gather", k_gather, (unsigned)xcd_span(c->n_rp), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
     LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, count_step);
     return PIC_OK;
@@ -432,7 +453,8 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
 #endif
 // n steps on a uniform mesh: the first step's advect, then n-1 times
 // (re-sort fused with the next advect), then the last re-sort.  Identical
-// arithmetic to n separate steps.
+// arithmetic to n separate steps.  The buffer flip after a fused advect is
+// done by the scan that follows it.
 pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec, int n)
 {
     const int pr = prec == PIC_F32;
@@ -442,14 +464,13 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
     BlockFn ff = block_kernel(c->mesh.dim, scheme, prec, true, ode, ti);
     LAUNCH(c, "advect", fa, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     for (int k = 1; k < n; ++k) {
-        pic_status s = enqueue_scan(c, dp, 0);
+        pic_status s = enqueue_scan(c, dp, 0, k > 1);
         if (s) return s;
-        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
-        LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
+        LAUNCH(c, "place", k_place_waves, place_grid(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        if ((s = enqueue_fix_sorted(c, dp))) return s;
         LAUNCH(c, "gather_advect", ff, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
-        LAUNCH(c, "flip", k_flip, 1u, 64u, dp, 1, 1);
     }
-    return enqueue_sort(c, dp, 1);
+    return enqueue_sort(c, dp, 1, false, n > 1);
 }
 
 pic_status enqueue_step(pic_ctx *c, ProblemDev *dp, int scheme, int prec)

@@ -50,10 +50,27 @@ __device__ __forceinline__ int64_t cell_value(const ProblemDev &P, int64_t K, in
     return (keep + add) | (add << 32);      // packed: count | additions << 32
 }
 
+// Flip the current buffer of a problem; a counted step also advances the time
+// since t^n of a field that changes in time.
+__device__ __forceinline__ void flip_problem(ProblemDev &P, int count_step)
+{
+    P.cur = 1 - P.cur;
+    if (count_step) {
+        atomicAdd(&P.scr.stats[ST_STEPS], 1ull);
+        if (P.ti) *P.tau = *P.tau + P.dt;
+    }
+}
+
+// Chunk totals of the counts.  A sequence of fused steps leaves the flip of
+// the step its last launch advanced to the next scan: mode 0 reads neither
+// the buffers nor the buffer index, so workgroup 0 flips problems
+// [0, flip_n) (counting the step) alongside the reduction.
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
-                                                       int n_items, int mode)
+                                                       int n_items, int mode, ProblemDev *flip_probs, int flip_n)
 {
     __shared__ int64_t s_tmp[BLOCK / 64];
+    if (blockIdx.x == 0)
+        for (int q = threadIdx.x; q < flip_n; q += BLOCK) flip_problem(flip_probs[q], 1);
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const ScanItem it = items[w];
         const ProblemDev &P = probs[it.problem];
@@ -129,9 +146,27 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
  * consecutive cells of the tile (their particles are consecutive), locates
  * each particle's cell from the run's cell starts, and ranks the stayers of
  * the run with a ballot per 64 particles (the stayers of a cell are the run's
- * stayers minus those of its earlier cells, whose counts are known).
+ * stayers minus those of its earlier cells, whose counts are known).  The
+ * particles are taken PLACE_BATCH chunks of 64 at a time: the chunks' keys
+ * are loaded together, then their cursor atomics are issued together (one
+ * per destination cell and chunk: the particles of a cell that leave it tend
+ * to leave for the same neighbour), then the arrivals' slots are written.
  */
 constexpr int PLACE_RUN = 16;
+#ifndef PIC_PLACE_BATCH
+#define PIC_PLACE_BATCH 2
+#endif
+constexpr int PLACE_BATCH = PIC_PLACE_BATCH;
+// index of the last of the run's first nr cells whose range starts at or
+// before slot sl (the starts are non-decreasing; aq holds them wave-uniform)
+__device__ __forceinline__ int run_cell(const int (&aq)[PLACE_RUN], int nr, int sl)
+{
+    int c = 0;
+#pragma unroll
+    for (int q = 1; q < PLACE_RUN; ++q) c += (q < nr && aq[q] <= sl) ? 1 : 0;
+    return c;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_place_waves(const ProblemDev *__restrict__ probs,
                                                        const WorkItem *__restrict__ work, int n_work)
 {
@@ -145,6 +180,8 @@ __global__ __launch_bounds__(BLOCK) void k_place_waves(const ProblemDev *__restr
         const StoreDev cur = P.store[P.cur];
         const StoreDev nxt = P.store[1 - P.cur];
         const uint32_t PIC_G *keys = P.scr.key[P.cur];
+        int32_t PIC_G *cursor = P.scr.cursor;
+        int32_t PIC_G *src = P.scr.src;
         for (int r0 = wi.c0 + wv * PLACE_RUN; r0 < wi.c1; r0 += (BLOCK / 64) * PLACE_RUN) {
             const int nr = min(PLACE_RUN, wi.c1 - r0);
             // lane q <= nr: old start of cell r0 + q (lane nr: the run's end);
@@ -161,26 +198,69 @@ __global__ __launch_bounds__(BLOCK) void k_place_waves(const ProblemDev *__restr
                 const int v = __shfl_up(ex, o, 64);
                 if (lane >= o) ex += v;
             }
-            ex -= s_q;                                  // stayers of the run's earlier cells
-            const int p0 = __shfl(a_q, 0, 64), p1 = __shfl(a_q, nr, 64);
-            int carry = 0;
-            for (int base = p0; base < p1; base += 64) {
-                const int pp = base + lane;
-                const bool valid = pp < p1;
-                int c = 0;                              // last cell of the run starting at or before pp
+            // the k-th stayer of the run (counting the earlier cells' stayers)
+            // that lies in cell q goes to slot d_q + k
+            const int d_q = b_q - (ex - s_q);
+            int aq[PLACE_RUN];
 #pragma unroll
-                for (int step = PLACE_RUN / 2; step >= 1; step >>= 1) {
-                    const int t = c + step;
-                    const int v = __shfl(a_q, t, 64);
-                    if (t < nr && v <= pp) c = t;
+            for (int q = 0; q < PLACE_RUN; ++q) aq[q] = __builtin_amdgcn_readlane(a_q, q);
+            const int p0 = aq[0], p1 = __shfl(a_q, nr, 64);
+            int carry = 0;
+            for (int base = p0; base < p1; base += 64 * PLACE_BATCH) {
+                uint32_t key[PLACE_BATCH];
+#pragma unroll
+                for (int u = 0; u < PLACE_BATCH; ++u) {
+                    const int pp = base + 64 * u + lane;
+                    key[u] = pp < p1 ? keys[pp] : LOST;
                 }
-                const uint32_t key = valid ? keys[pp] : LOST;
-                const bool stay = valid && key == (uint32_t)(r0 + c);
-                const unsigned long long mm = __ballot(stay);
-                const int bc = __shfl(b_q, c, 64), ec = __shfl(ex, c, 64);
-                if (stay) P.scr.src[bc + carry + __popcll(mm & below) - ec] = pp;
-                else if (key != LOST) P.scr.src[atomicAdd(&P.scr.cursor[key], 1)] = pp;
-                carry += __popcll(mm);
+                // stayers' slots by ballot (written at once)
+                uint32_t arr = 0;
+#pragma unroll
+                for (int u = 0; u < PLACE_BATCH; ++u) {
+                    const int pp = base + 64 * u + lane;
+                    const int c = run_cell(aq, nr, pp);
+                    const bool stay = pp < p1 && key[u] == (uint32_t)(r0 + c);
+                    const unsigned long long mm = __ballot(stay);
+                    const int sl = __shfl(d_q, c, 64) + carry + __popcll(mm & below);
+                    if (stay) src[sl] = pp;
+                    arr |= (uint32_t)(!stay && key[u] != LOST) << u;
+                    carry += __popcll(mm);
+                }
+                // arrivals: the lanes of a chunk with one destination take
+                // consecutive slots in lane order from one atomic, issued by
+                // the first of them (lane lead)
+                int lead[PLACE_BATCH], rank[PLACE_BATCH], aslot[PLACE_BATCH];
+#pragma unroll
+                for (int u = 0; u < PLACE_BATCH; ++u) {
+                    const bool mine = (arr >> u) & 1u;
+                    unsigned long long todo = __ballot(mine);
+                    int cnt = 0;
+                    lead[u] = 0;
+                    rank[u] = 0;
+                    while (todo) {
+                        const int l = __ffsll((long long)todo) - 1;
+                        const uint32_t k = __builtin_amdgcn_readlane(key[u], l);
+                        const unsigned long long m = __ballot(mine && key[u] == k);
+                        if ((m >> lane) & 1ull) {
+                            lead[u] = l;
+                            rank[u] = __popcll(m & below);
+                        }
+                        if (lane == l) cnt = __popcll(m);
+                        todo &= ~m;
+                    }
+                    if (cnt) aslot[u] = atomicAdd(&cursor[key[u]], cnt);
+                }
+                // the slots are read in straight-line code, so that one wait
+                // covers all the atomics (read inside the stores' branches,
+                // each would wait for all memory operations again)
+#pragma unroll
+                for (int u = 0; u < PLACE_BATCH; ++u) {
+                    asm volatile("" : "+v"(aslot[u]));
+                    aslot[u] = __shfl(aslot[u], lead[u], 64) + rank[u];
+                }
+#pragma unroll
+                for (int u = 0; u < PLACE_BATCH; ++u)
+                    if ((arr >> u) & 1u) src[aslot[u]] = base + 64 * u + lane;
             }
         }
     }
@@ -425,13 +505,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const ProblemDev *__restrict__
 __global__ void k_flip(ProblemDev *probs, int n_probs, int count_step)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n_probs) {
-        probs[p].cur = 1 - probs[p].cur;
-        if (count_step) {
-            atomicAdd(&probs[p].scr.stats[ST_STEPS], 1ull);
-            if (probs[p].ti) *probs[p].tau = *probs[p].tau + probs[p].dt;
-        }
-    }
+    if (p < n_probs) flip_problem(probs[p], count_step);
 }
 
 // ===========================================================================
