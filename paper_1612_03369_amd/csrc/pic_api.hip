@@ -227,7 +227,7 @@ void free_mesh(pic_ctx *c)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int64_t n_chunks(int64_t nc) { return (nc + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+int64_t n_chunks(int64_t nc) { return (nc + scan_chunk_cells(nc) - 1) / scan_chunk_cells(nc); }
 
 // Layout of the caller's scratch buffer.
 size_t scratch_layout(int64_t cap, int64_t nc, char *base, ScratchDev *s)

@@ -14,6 +14,13 @@ namespace pic {
 constexpr uint32_t LOST = 0xFFFFFFFFu;
 constexpr double NEAR_TOL = 1e-10;   // near-face band in reference coordinates
 constexpr int BLOCK = 256;           // threads per workgroup of the per-tile kernels
+// Cells per thread of the scan's chunks (BLOCK threads per chunk): meshes of up
+// to 2^19 cells take short chunks (more workgroups, shorter load chains), larger
+// ones long chunks, so that the sum over the preceding chunks' totals that each
+// workgroup of the down-sweep forms stays short.
+constexpr int SCAN_PT_MAX = 8;
+__host__ __device__ inline int scan_per_thread(int64_t n_cells) { return n_cells <= (int64_t(1) << 19) ? 2 : SCAN_PT_MAX; }
+__host__ __device__ inline int64_t scan_chunk_cells(int64_t n_cells) { return (int64_t)BLOCK * scan_per_thread(n_cells); }
 constexpr int MAX_TILE = 1024;       // cells per work item (LDS arrays are sized by it)
 constexpr int MAX_NBR = 64;          // vertex neighbours of one cell (octree upper bound)
 #ifndef PIC_EVAL_BATCH

@@ -12,8 +12,6 @@ namespace pic {
 // ===========================================================================
 // scan of the new per-cell counts (two phases over chunks of cells)
 // ===========================================================================
-constexpr int SCAN_PER_THREAD = 8;
-constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 
 // int64 workgroup exclusive scan; returns the prefix, sets total.
 __device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t *s_tmp, int64_t &total)
@@ -74,10 +72,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restr
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const ScanItem it = items[w];
         const ProblemDev &P = probs[it.problem];
+        const int pt = scan_per_thread(P.mesh.n_cells);
         int64_t sum = 0;
-        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-            int64_t K = (int64_t)it.chunk * SCAN_CHUNK + (int64_t)k * BLOCK + threadIdx.x;
-            if (K < P.mesh.n_cells) sum += cell_value(P, K, mode);
+#pragma unroll
+        for (int k = 0; k < SCAN_PT_MAX; ++k) {
+            const int64_t K = (int64_t)it.chunk * BLOCK * pt + (int64_t)k * BLOCK + threadIdx.x;
+            if (k < pt && K < P.mesh.n_cells) sum += cell_value(P, K, mode);
         }
         int64_t total;
         block_scan_i64(sum, s_tmp, total);
@@ -99,22 +99,25 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
         const ProblemDev &P = probs[it.problem];
         const int64_t nc = P.mesh.n_cells;
         const StoreDev nxt = P.store[1 - P.cur];
-        int64_t v[SCAN_PER_THREAD];
+        const int pt = scan_per_thread(nc);
+        int64_t v[SCAN_PT_MAX];
         int64_t sum = 0;
-        const int64_t K0 = (int64_t)it.chunk * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER_THREAD;
-        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-            int64_t K = K0 + k;
-            v[k] = K < nc ? cell_value(P, K, mode) : 0;
+        const int64_t K0 = (int64_t)it.chunk * BLOCK * pt + (int64_t)threadIdx.x * pt;
+#pragma unroll
+        for (int k = 0; k < SCAN_PT_MAX; ++k) {
+            const int64_t K = K0 + k;
+            v[k] = k < pt && K < nc ? cell_value(P, K, mode) : 0;
             sum += v[k];
         }
         int64_t before = 0, offset, total;
         for (int c = threadIdx.x; c < it.chunk; c += BLOCK) before += P.scr.chunk[c];
         block_scan_i64(before, s_tmp, offset);
         int64_t run = block_scan_i64(sum, s_tmp, total) + offset;
-        const int64_t nch = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
-        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-            int64_t K = K0 + k;
-            if (K < nc) {
+        const int64_t nch = (nc + (int64_t)BLOCK * pt - 1) / ((int64_t)BLOCK * pt);
+#pragma unroll
+        for (int k = 0; k < SCAN_PT_MAX; ++k) {
+            const int64_t K = K0 + k;
+            if (k < pt && K < nc) {
                 if (mode == 0) {
                     nxt.cs[K] = (int32_t)run;
                     P.scr.n_arrive[K] = 0;
