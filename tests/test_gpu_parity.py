@@ -134,20 +134,23 @@ def test_box_domain_and_long_steps(L, dim, cfl):
     p.close()
 
 
-def test_sort_is_pure_function_of_gpu_keys(L):
+@pytest.mark.parametrize("dim,n,per_cell,steps", [(3, 12, 9, 6),
+                                                  # more than 2^19 cells: the scan's long chunks
+                                                  (2, 768, 2, 3)])
+def test_sort_is_pure_function_of_gpu_keys(L, dim, n, per_cell, steps):
     """Each step's new order = stable sort of the previous order by (new cell, moved): a property
     of the GPU's own keys, checked with NumPy's stable argsort (the oracle is not involved)."""
-    _say("case: sort permutation vs a stable argsort of the GPU's own keys")
-    mesh = I.UniformMesh(3, (12, 12, 12))
-    f = I.FourierField(3, seed=77)
+    _say(f"case: sort permutation vs a stable argsort of the GPU's own keys, {dim}D n={n}")
+    mesh = I.UniformMesh(dim, (n,) * dim)
+    f = I.FourierField(dim, seed=77)
     U = I.normalise_nodal(I.sample_nodes(f.velocity, I.uniform_q2_nodes(mesh)))
-    counts = np.full(mesh.n_cells, 9, np.int32)
-    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=78)
+    counts = np.full(mesh.n_cells, per_cell, np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, dim, seed=78)
     cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=0, prop_dtype=np.float64)
     p = gpu_problem(cfg)
-    for step in range(6):
+    for step in range(steps):
         a = p.numpy()
-        p.advance(1.2 / 12, 1, L.PIC_RK4, L.PIC_F64)        # CFL 1.2: many movers, some two cells away
+        p.advance(1.2 / n, 1, L.PIC_RK4, L.PIC_F64)         # CFL 1.2: many movers, some two cells away
         b = p.numpy()
         pos = {int(i): k for k, i in enumerate(b["id"])}
         lost = np.uint32(0xFFFFFFFF)
