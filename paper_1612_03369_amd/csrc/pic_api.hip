@@ -403,23 +403,21 @@ pic_status set_dt(pic_ctx *c, double dt)
     return PIC_OK;
 }
 
-// scan (mode 0: stayers + arrivals, 1: population packed, 2: n_arrive only);
-// flip: the buffer flip of a fused step is still pending (mode 0 only)
-pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode, bool flip = false)
+// scan (mode 0: stayers + arrivals, 1: population packed); flip: the buffer
+// flip of a fused step is still pending (mode 0 only)
+template <int MODE, int PT> pic_status enqueue_scan_t(pic_ctx *c, ProblemDev *dp, bool flip)
 {
-    LAUNCH(c, "scan_reduce", k_scan_reduce, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode,
-           dp, flip ? 1 : 0);
-    LAUNCH(c, "scan_down", k_scan_down, (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan, c->n_scan, mode);
+    LAUNCH(c, "scan_reduce", (k_scan_reduce<MODE, PT>), (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan,
+           c->n_scan, dp, flip ? 1 : 0);
+    LAUNCH(c, "scan_down", (k_scan_down<MODE, PT>), (unsigned)c->n_scan, BLOCK, (const ProblemDev *)dp, (const ScanItem *)c->d_scan,
+           c->n_scan);
     return PIC_OK;
 }
-
-#ifndef PIC_PLACE_GRID_MAX
-#define PIC_PLACE_GRID_MAX 0
-#endif
-unsigned place_grid(int n_work)
+pic_status enqueue_scan(pic_ctx *c, ProblemDev *dp, int mode, bool flip = false)
 {
-    const int g = xcd_span(n_work);
-    return (unsigned)(PIC_PLACE_GRID_MAX > 0 && g > PIC_PLACE_GRID_MAX ? PIC_PLACE_GRID_MAX : g);
+    const bool short_chunks = scan_per_thread(c->mesh.n_cells) == 2;
+    if (mode == 0) return short_chunks ? enqueue_scan_t<0, 2>(c, dp, flip) : enqueue_scan_t<0, SCAN_PT_MAX>(c, dp, flip);
+    return short_chunks ? enqueue_scan_t<1, 2>(c, dp, false) : enqueue_scan_t<1, SCAN_PT_MAX>(c, dp, false);
 }
 
 // arrival order after the placement of a buffer sorted by cell
@@ -440,7 +438,7 @@ pic_status enqueue_sort(pic_ctx *c, ProblemDev *dp, int count_step, bool unsorte
         LAUNCH(c, "place", k_place_unsorted, (unsigned)c->n_rp, BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
         LAUNCH(c, "fix", k_fix, (unsigned)xcd_span(c->n_rc), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rc, c->n_rc);
     } else {
-        LAUNCH(c, "place", k_place_waves, place_grid(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
         if ((s = enqueue_fix_sorted(c, dp))) return s;
     }
     LAUNCH(c, "gather", k_gather, (unsigned)xcd_span(c->n_rp), BLOCK, (const ProblemDev *)dp, (const RangeItem *)c->d_rp, c->n_rp);
@@ -466,7 +464,7 @@ pic_status enqueue_steps_fused(pic_ctx *c, ProblemDev *dp, int scheme, int prec,
     for (int k = 1; k < n; ++k) {
         pic_status s = enqueue_scan(c, dp, 0, k > 1);
         if (s) return s;
-        LAUNCH(c, "place", k_place_waves, place_grid(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
+        LAUNCH(c, "place", k_place_waves, (unsigned)xcd_span(c->n_work), BLOCK, (const ProblemDev *)dp, (const WorkItem *)c->d_work, c->n_work);
         if ((s = enqueue_fix_sorted(c, dp))) return s;
         LAUNCH(c, "gather_advect", ff, (unsigned)xcd_span(c->n_blk[pr]), ADV_BLOCK, (const ProblemDev *)dp, (const BlockItem *)c->d_blk[pr], c->n_blk[pr]);
     }

@@ -37,16 +37,35 @@ __device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t *s_tmp, int
     return off + inc - v;
 }
 
-// count of cell K after the step (stayers + arrivals); mode 1 = population clamp
-__device__ __forceinline__ int64_t cell_value(const ProblemDev &P, int64_t K, int mode)
-{
-    if (mode == 0) return (int64_t)P.scr.n_stay[K] + (int64_t)P.scr.n_arrive[K];
-    const StoreDev cur = P.store[P.cur];
-    int64_t n = cur.cs[K + 1] - cur.cs[K];
-    int64_t keep = n > P.pop_max ? P.pop_max : n;
-    int64_t add = keep < P.pop_min ? P.pop_min - keep : 0;
-    return (keep + add) | (add << 32);      // packed: count | additions << 32
-}
+// Count of a cell after the step from the two words loaded for it: stayers +
+// arrivals (MODE 0: x = n_stay[K], y = n_arrive[K]), or the population clamp
+// (MODE 1: x = cs[K], y = cs[K + 1] of the current buffer; packed as
+// count | additions << 32).  The words of all of a thread's cells are loaded
+// before the first is used, so that the loads are in flight together.
+template <int MODE> struct CellWords {
+    const int32_t PIC_G *x, *y;
+    int pop_min, pop_max;
+    __device__ __forceinline__ explicit CellWords(const ProblemDev &P)
+    {
+        if (MODE == 0) {
+            x = P.scr.n_stay;
+            y = P.scr.n_arrive;
+        } else {
+            x = P.store[P.cur].cs;
+            y = x + 1;
+        }
+        pop_min = P.pop_min;
+        pop_max = P.pop_max;
+    }
+    __device__ __forceinline__ int64_t value(int32_t a, int32_t b) const
+    {
+        if (MODE == 0) return (int64_t)a + (int64_t)b;
+        const int64_t n = (int64_t)b - a;
+        const int64_t keep = n > pop_max ? pop_max : n;
+        const int64_t add = keep < pop_min ? pop_min - keep : 0;
+        return (keep + add) | (add << 32);
+    }
+};
 
 // Flip the current buffer of a problem; a counted step also advances the time
 // since t^n of a field that changes in time.
@@ -62,23 +81,36 @@ __device__ __forceinline__ void flip_problem(ProblemDev &P, int count_step)
 // Chunk totals of the counts.  A sequence of fused steps leaves the flip of
 // the step its last launch advanced to the next scan: mode 0 reads neither
 // the buffers nor the buffer index, so workgroup 0 flips problems
-// [0, flip_n) (counting the step) alongside the reduction.
+// [0, flip_n) (counting the step) alongside the reduction.  PT: cells per
+// thread of the chunks (0: from each problem's mesh, for launches over
+// several problems).
+template <int MODE, int PT>
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
-                                                       int n_items, int mode, ProblemDev *flip_probs, int flip_n)
+                                                       int n_items, ProblemDev *flip_probs, int flip_n)
 {
+    constexpr int NK = PT ? PT : SCAN_PT_MAX;
     __shared__ int64_t s_tmp[BLOCK / 64];
     if (blockIdx.x == 0)
         for (int q = threadIdx.x; q < flip_n; q += BLOCK) flip_problem(flip_probs[q], 1);
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const ScanItem it = items[w];
         const ProblemDev &P = probs[it.problem];
-        const int pt = scan_per_thread(P.mesh.n_cells);
+        const int64_t nc = P.mesh.n_cells;
+        const int pt = PT ? PT : scan_per_thread(nc);
+        const CellWords<MODE> cw(P);
+        int32_t a[NK], b[NK];
+        bool ok[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int64_t K = (int64_t)it.chunk * BLOCK * pt + (int64_t)k * BLOCK + threadIdx.x;
+            ok[k] = k < pt && K < nc;
+            const int64_t Kc = ok[k] ? K : 0;
+            a[k] = cw.x[Kc];
+            b[k] = cw.y[Kc];
+        }
         int64_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_PT_MAX; ++k) {
-            const int64_t K = (int64_t)it.chunk * BLOCK * pt + (int64_t)k * BLOCK + threadIdx.x;
-            if (k < pt && K < P.mesh.n_cells) sum += cell_value(P, K, mode);
-        }
+        for (int k = 0; k < NK; ++k) sum += ok[k] ? cw.value(a[k], b[k]) : 0;
         int64_t total;
         block_scan_i64(sum, s_tmp, total);
         if (threadIdx.x == 0) P.scr.chunk[it.chunk] = total;
@@ -89,39 +121,51 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const ProblemDev *__restr
 // offset is the sum of the preceding chunks' totals of its problem, added up
 // by the workgroup itself (a few hundred values at most).  Mode 0 also
 // resets the arrival counters and sets each cell's placement cursor to its
-// first arrival slot (after its stayers).
+// first arrival slot (after its stayers).  PT as for k_scan_reduce.
+template <int MODE, int PT>
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restrict__ probs, const ScanItem *__restrict__ items,
-                                                     int n_items, int mode)
+                                                     int n_items)
 {
+    constexpr int NK = PT ? PT : SCAN_PT_MAX;
     __shared__ int64_t s_tmp[BLOCK / 64];
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const ScanItem it = items[w];
         const ProblemDev &P = probs[it.problem];
         const int64_t nc = P.mesh.n_cells;
         const StoreDev nxt = P.store[1 - P.cur];
-        const int pt = scan_per_thread(nc);
-        int64_t v[SCAN_PT_MAX];
-        int64_t sum = 0;
+        const int pt = PT ? PT : scan_per_thread(nc);
+        const CellWords<MODE> cw(P);
         const int64_t K0 = (int64_t)it.chunk * BLOCK * pt + (int64_t)threadIdx.x * pt;
+        int32_t a[NK], b[NK];
+        bool ok[NK];
 #pragma unroll
-        for (int k = 0; k < SCAN_PT_MAX; ++k) {
+        for (int k = 0; k < NK; ++k) {
             const int64_t K = K0 + k;
-            v[k] = k < pt && K < nc ? cell_value(P, K, mode) : 0;
-            sum += v[k];
+            ok[k] = k < pt && K < nc;
+            const int64_t Kc = ok[k] ? K : 0;
+            a[k] = cw.x[Kc];
+            b[k] = cw.y[Kc];
         }
         int64_t before = 0, offset, total;
         for (int c = threadIdx.x; c < it.chunk; c += BLOCK) before += P.scr.chunk[c];
+        int64_t v[NK];
+        int64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            v[k] = ok[k] ? cw.value(a[k], b[k]) : 0;
+            sum += v[k];
+        }
         block_scan_i64(before, s_tmp, offset);
         int64_t run = block_scan_i64(sum, s_tmp, total) + offset;
         const int64_t nch = (nc + (int64_t)BLOCK * pt - 1) / ((int64_t)BLOCK * pt);
 #pragma unroll
-        for (int k = 0; k < SCAN_PT_MAX; ++k) {
+        for (int k = 0; k < NK; ++k) {
             const int64_t K = K0 + k;
-            if (k < pt && K < nc) {
-                if (mode == 0) {
+            if (ok[k]) {
+                if (MODE == 0) {
                     nxt.cs[K] = (int32_t)run;
                     P.scr.n_arrive[K] = 0;
-                    P.scr.cursor[K] = (int32_t)run + P.scr.n_stay[K];
+                    P.scr.cursor[K] = (int32_t)run + a[k];          // after the cell's stayers
                 } else {
                     nxt.cs[K] = (int32_t)(run & 0xFFFFFFFFll);
                     P.scr.cursor[K] = (int32_t)(run >> 32);     // first new-id offset of the cell
@@ -131,8 +175,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const ProblemDev *__restric
         }
         if (it.chunk == nch - 1 && threadIdx.x == 0) {
             const int64_t tot = offset + total;
-            nxt.cs[nc] = (int32_t)(mode == 0 ? tot : (tot & 0xFFFFFFFFll));
-            if (mode == 1) P.scr.cursor[nc] = (int32_t)(tot >> 32);
+            nxt.cs[nc] = (int32_t)(MODE == 0 ? tot : (tot & 0xFFFFFFFFll));
+            if (MODE == 1) P.scr.cursor[nc] = (int32_t)(tot >> 32);
         }
     }
 }
