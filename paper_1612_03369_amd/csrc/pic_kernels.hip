@@ -391,6 +391,9 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 // (the positions are distinct) is its slot; beyond what LDS holds, the ranks
 // are counted over LDS-sized tiles (n^2 / 256 LDS reads per thread).
 constexpr int FIX_LDS = 32;
+#ifndef PIC_FIX_REGS
+#define PIC_FIX_REGS 1
+#endif
 
 // Sort a[0..nn) (distinct values) by the whole workgroup: each value's rank
 // among the others is its place.  In LDS while the values and their sorted
@@ -462,6 +465,19 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
             const int slot = atomicAdd(&s_nbig, 1);
             s_big_b[slot] = b;
             s_big_n[slot] = n;
+        } else if (n >= 2 && n <= 8 && PIC_FIX_REGS) {
+            // up to eight arrivals (the common case) ranked in registers
+            auto a = (gptr_mut<int32_t>)(P.scr.src + b);
+            int32_t r[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = a[min(q, n - 1)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int k = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) k += (j < n && r[j] < r[q]) ? 1 : 0;
+                if (q < n && k != q) a[k] = r[q];
+            }
         } else if (n >= 2) {
             auto a = (gptr_mut<int32_t>)(P.scr.src + b);
             int32_t *v = s_v + threadIdx.x;
