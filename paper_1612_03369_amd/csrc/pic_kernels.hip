@@ -392,8 +392,25 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 // are counted over LDS-sized tiles (n^2 / 256 LDS reads per thread).
 constexpr int FIX_LDS = 32;
 #ifndef PIC_FIX_REGS
-#define PIC_FIX_REGS 1
+#define PIC_FIX_REGS 1                  // 1: up to 8 arrivals ranked in registers; 2: up to 16
 #endif
+
+// Sort a[0..n) (distinct values, 2 <= n <= R) in place: every value is loaded
+// into registers (loads past the end re-read the last one), and each goes to
+// its rank among the others; only the slots whose value changes are written.
+template <int R> __device__ __forceinline__ void rank_in_registers(int32_t PIC_G *a, int n)
+{
+    int32_t r[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) r[q] = a[min(q, n - 1)];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        int k = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) k += (j < n && r[j] < r[q]) ? 1 : 0;
+        if (q < n && k != q) a[k] = r[q];
+    }
+}
 
 // Sort a[0..nn) (distinct values) by the whole workgroup: each value's rank
 // among the others is its place.  In LDS while the values and their sorted
@@ -467,17 +484,9 @@ __global__ __launch_bounds__(BLOCK) void k_fix(const ProblemDev *__restrict__ pr
             s_big_n[slot] = n;
         } else if (n >= 2 && n <= 8 && PIC_FIX_REGS) {
             // up to eight arrivals (the common case) ranked in registers
-            auto a = (gptr_mut<int32_t>)(P.scr.src + b);
-            int32_t r[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) r[q] = a[min(q, n - 1)];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                int k = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) k += (j < n && r[j] < r[q]) ? 1 : 0;
-                if (q < n && k != q) a[k] = r[q];
-            }
+            rank_in_registers<8>((gptr_mut<int32_t>)(P.scr.src + b), n);
+        } else if (n >= 2 && n <= 16 && PIC_FIX_REGS > 1) {
+            rank_in_registers<16>((gptr_mut<int32_t>)(P.scr.src + b), n);
         } else if (n >= 2) {
             auto a = (gptr_mut<int32_t>)(P.scr.src + b);
             int32_t *v = s_v + threadIdx.x;
