@@ -384,9 +384,10 @@ __global__ __launch_bounds__(BLOCK) void k_place_unsorted(const ProblemDev *__re
 
 // Sort each cell's arrivals by their previous position (= previous global
 // order, since the previous store was sorted by cell); one thread per cell.
-// Up to FIX_LDS arrivals are ranked in LDS (thread t's list interleaved with
-// the others' so that the threads of a wave hit distinct banks).  Cells with
-// more (an unsorted input, a coarsened mesh) are sorted afterwards one at a
+// Up to eight arrivals (most cells) are ranked in registers, up to FIX_LDS
+// in LDS (thread t's list interleaved with the others' so that the threads of
+// a wave hit distinct banks).  Cells with more (an unsorted input, a
+// coarsened mesh) are sorted afterwards one at a
 // time by the whole workgroup: each arrival's rank among the cell's arrivals
 // (the positions are distinct) is its slot; beyond what LDS holds, the ranks
 // are counted over LDS-sized tiles (n^2 / 256 LDS reads per thread).
