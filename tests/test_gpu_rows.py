@@ -175,6 +175,33 @@ def test_batch_bit_identical_to_single_runs(L, schedule):
         p.close()
 
 
+def test_batch_with_long_and_short_scan_chunks(L):
+    """A batch whose problems take different scan chunk widths (one mesh of more than 2^19
+    cells, two small ones) equals the single runs bit for bit."""
+    _say("case: batch with a 768^2 mesh (long scan chunks) and two small meshes vs single runs")
+    from paper_1612_03369_amd.api import Batch
+    cfgs = [_fourier_cfg(2, 768, 3, seed=251), _fourier_cfg(3, 8, 10, seed=252), _fourier_cfg(2, 20, 10, seed=253)]
+    for c, sch in zip(cfgs, (4, 2, 4)):
+        c["scheme"] = sch
+        c["dt"] = 0.5 / c["mesh"].n[0]
+    singles = []
+    for c in cfgs:
+        p = gpu_problem(c)
+        p.advance(c["dt"], 5, c["scheme"], L.PIC_F64)
+        singles.append(p.numpy())
+        p.close()
+    probs = [gpu_problem(c) for c in cfgs]
+    b = Batch(probs)
+    b.advance([c["dt"] for c in cfgs], [c["scheme"] for c in cfgs], 5)
+    for p, s in zip(probs, singles):
+        g = p.numpy()
+        for k in ("x", "xr", "cell", "id", "prop", "cell_start"):
+            assert np.array_equal(g[k], s[k]), k
+    b.close()
+    for p in probs:
+        p.close()
+
+
 # ----------------------------------------------------------------------------
 def _adjoint_case(L, n=6, ppc=3, steps=8, scheme=4, ckpt=3, seed=301, dim=3):
     mesh = I.UniformMesh(dim, (n,) * dim)
