@@ -168,6 +168,33 @@ def test_sort_is_pure_function_of_gpu_keys(L, dim, n, per_cell, steps):
     p.close()
 
 
+@pytest.mark.parametrize("tile", [1, 16, 100, 300])
+def test_results_independent_of_the_tile(L, tile):
+    """The work tiles (placement runs, fix ranges, generic advect) change the launch shape only: a
+    run with tiles of 1, 16, 100 or 300 cells (partial placement runs, runs that cross no tile
+    boundary) equals the run with the default tile bit for bit, single and fused steps."""
+    _say(f"case: tile of {tile} cells vs the default tile")
+    mesh = I.UniformMesh(3, (12, 12, 12))
+    f = I.FourierField(3, seed=81)
+    U = I.normalise_nodal(I.sample_nodes(f.velocity, I.uniform_q2_nodes(mesh)))
+    counts = np.random.default_rng(82).integers(0, 14, mesh.n_cells).astype(np.int32)
+    counts, xr, ids = I.draw_reference_particles(counts, 3, seed=83)
+    cfg = dict(mesh=mesh, U=U, counts=counts, xr=xr, ids=ids, n_prop=1, prop_dtype=np.float64)
+    out = []
+    for t in (None, tile):
+        p = gpu_problem(cfg)
+        if t is not None:
+            p.set_tile(t)
+        p.advance(1.2 / 12, 1, L.PIC_RK4, L.PIC_F64)
+        p.advance(1.2 / 12, 5, L.PIC_RK4, L.PIC_F32)
+        out.append((p.numpy(), p.stats()))
+        p.close()
+    (a, sa), (b, sb) = out
+    for k in ("x", "xr", "cell", "id", "prop", "cell_start"):
+        assert np.array_equal(a[k], b[k]), k
+    assert sa["moved"] == sb["moved"] and sa["lost"] == sb["lost"] and sa["moved"] > 100
+
+
 def test_empty_single_and_all_lost(L):
     _say("case: empty store, one particle, everything lost")
     mesh = I.UniformMesh(2, (5, 3))
